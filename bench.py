@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the qudit gate-application path on one MI355X.
+
+Workload (one step): the hybrid register of 10 qubits + 8 qutrits + 2 ququarts
+(D = 2^10 3^8 4^2 = 107,495,424 amplitudes, complex128) is set to |0...0>, the 500 seeded gates
+(Haar d x d unitaries on single qudits and controlled shifts on qudit pairs) are applied one by
+one through the C ABI, and the FP64 probabilities and the squared norm are read out.
+
+value = amplitude-updates/s over the timed steps (an uncontrolled gate updates D amplitudes, a
+controlled one D / prod d_c). Every gate launch is bracketed by HIP events on the stream the
+library launches on; the dominant kernel's average duration gives the roofline figure.
+
+Extras in the same JSON line (outside the timed steps): the streaming-copy HBM ceiling, the
+fused complex64 paths (FP32 / split-BF16 matrix cores) against the complex128 plain path on
+the qudit QFT, the batched path, and the oracle timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "amplitude-updates/s + HBM GB/s; fused FP32 vs plain FP64 at ≤1e-6 fidelity loss"
+HBM_PEAK_GBPS = 8000.0
+ROUTE_NAMES = {0: "k_slices_direct", 1: "k_slices_tiled", 2: "k_diag", 3: "k_dense_generic"}
+CLASS_NAMES = {0: "dense", 1: "monomial", 2: "diagonal"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def gate_plan(circ, Q):
+    import numpy as np
+    D = circ.D
+    out = []
+    for g in circ.gates:
+        U = Q.gate_unitary(g, circ.dims)
+        dc = int(np.prod([circ.dims[c] for c in g.controls])) if g.controls else 1
+        route = Q.qd_gate_route(circ.dims, Q.QD_C128, g.targets, g.controls, g.cvals, U)
+        cls = Q.qd_gate_class(U)
+        out.append({"t": list(g.targets), "c": list(g.controls), "v": list(g.cvals), "U": U,
+                    "active": D // dc, "key": (route, cls, U.shape[0])})
+    return out
+
+
+def kernel_name(key):
+    route, cls, dT = key
+    if route == 2:
+        return "k_diag<double>"
+    if route == 3:
+        return "k_dense_generic<double>"
+    op = "DenseOp" if cls == 0 else "MonoOp"
+    return f"{ROUTE_NAMES[route]}<double, {dT}, {op}<double, {dT}>>"
+
+
+def bench_plain(args, Q, torch, circ):
+    import numpy as np
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = gate_plan(circ, Q)
+    D = circ.D
+    s = Q.qd_state_init(circ.dims, Q.QD_C128, stream)
+    probs = torch.empty(D, dtype=torch.float64, device="cuda")
+    zeros = [0] * len(circ.dims)
+
+    def step(ev=None):
+        Q.qd_state_set_basis(s, zeros)
+        for i, g in enumerate(plan):
+            if ev is not None:
+                ev[i][0].record()
+            Q.qd_apply_gate(s, g["t"], g["c"], g["v"], g["U"])
+            if ev is not None:
+                ev[i][1].record()
+        Q.qd_probabilities(s, probs.data_ptr())
+        return Q.qd_norm2(s)
+
+    for _ in range(args.warmup):
+        step()
+    events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in plan]
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norms = [step(events[k]) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Q.qd_state_free(s)
+
+    per_key = {}
+    for k in range(args.steps):
+        for i, g in enumerate(plan):
+            ms = events[k][i][0].elapsed_time(events[k][i][1])
+            d = per_key.setdefault(g["key"], {"ms": 0.0, "n": 0, "bytes": 0.0})
+            d["ms"] += ms
+            d["n"] += 1
+            d["bytes"] += 2.0 * 16.0 * g["active"]
+    dom_key = max(per_key, key=lambda k: per_key[k]["ms"])
+    dom = per_key[dom_key]
+    avg_ms = dom["ms"] / dom["n"]
+    bytes_per_launch = dom["bytes"] / dom["n"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    upd = sum(g["active"] for g in plan)
+    total_bytes = sum(2.0 * 16.0 * g["active"] for g in plan)
+    gate_ms = sum(v["ms"] for v in per_key.values()) / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kernels = {kernel_name(k): {"launches_per_step": v["n"] // args.steps, "avg_us": 1e3 * v["ms"] / v["n"],
+                                "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+               for k, v in sorted(per_key.items(), key=lambda kv: -kv[1]["ms"])}
+    return {
+        "ms_per_step": ms_per_step,
+        "value": upd * args.steps / (t1 - t0),
+        "gates_per_s": len(plan) * args.steps / (t1 - t0),
+        "hbm_GBps_gates": total_bytes / (gate_ms * 1e-3) / 1e9,
+        "norm_drift": max(abs(n - 1.0) for n in norms),
+        "roofline": {"bound": "hbm", "kernel": kernel_name(dom_key), "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "kernels": kernels,
+    }
+
+
+def bench_copy(Q, torch):
+    stream = torch.cuda.current_stream().cuda_stream
+    nbytes = 4 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        Q.qd_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        Q.qd_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def bench_cpu(circ, seconds):
+    """The oracle (never tuned) on the full register, gate by gate from |0...0>, on one host
+    thread, until `seconds` of work are done."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover - threadpoolctl is installed
+        limiter = None
+    dims = circ.dims
+    psi = O.basis_state(dims)
+    upd = 0
+    n = 0
+    t0 = time.perf_counter()
+    for g in circ.gates:
+        psi = O.apply_gate(psi, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+        dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
+        upd += circ.D // dc
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": upd / dt, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {len(circ.gates)} gates of the same workload at full size "
+                      f"(D={circ.D}), NumPy complex128 contraction, 1 BLAS thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(a multi-GPU run would shard the register, which this build does not do)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import circuits as C
+    import paper_2211_07918_amd as Q
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    Q.load()
+    circ = C.config1()
+    log(f"plain complex128: D={circ.D} gates={len(circ.gates)} steps={args.steps} warmup={args.warmup}")
+    plain = bench_plain(args, Q, torch, circ)
+    log(f"plain: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} amp-upd/s, "
+        f"dominant {plain['roofline']['kernel']} {plain['roofline']['achieved']:.0f} GB/s")
+    extras = {}
+    if not args.no_extras:
+        extras["copy_ceiling"] = bench_copy(Q, torch)
+        log(f"copy ceiling: {extras['copy_ceiling']['GBps']:.0f} GB/s")
+    out = {
+        "metric": METRIC,
+        "value": plain["value"],
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": plain["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded circuits; no dataset)",
+        "config": {"workload": "hybrid register 10 qubits + 8 qutrits + 2 ququarts, 500 seeded gates "
+                               "(Haar d x d / controlled shifts), complex128 plain path + FP64 readout",
+                   "D": circ.D, "gates": len(circ.gates), "precision": "complex128"},
+        "gates_per_s": plain["gates_per_s"],
+        "hbm_GBps": plain["hbm_GBps_gates"],
+        "norm_drift": plain["norm_drift"],
+        "roofline": plain["roofline"],
+        "kernels": plain["kernels"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = bench_cpu(circ, args.cpu_seconds)
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} amp-upd/s")
+    if extras:
+        out["extras"] = extras
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

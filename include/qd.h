@@ -1,0 +1,299 @@
+/*
+ * qd.h - C ABI of libqd, an MI355X (gfx950) engine that applies generalized qudit gates to a dense
+ * complex state vector over a mixed-radix register.
+ *
+ * Method: QuDiet (arXiv 2211.07918). The paper simulates a circuit by forming, per Moment, the
+ * Kronecker product of the gates acting on every wire, multiplying those operators and applying
+ * the product to the initial state (Sec. 3.5-3.6). libqd computes the same result gate by gate:
+ * applying the Kronecker-embedded operator I (x) U (x) I of one gate to the state costs O(D d_T)
+ * instead of O(D^2).
+ *
+ * Conventions (apply to every call):
+ *   - A register is a list of qudit dimensions dims[0..n-1]; its state has D = prod dims[i]
+ *     amplitudes (Sec. 2.2). The flat index is big-endian mixed radix: qudit 0 is the most
+ *     significant digit, stride s_i = prod_{j>i} dims[j] (the Kronecker order of Sec. 3.3, Eq. (3),
+ *     and the ket labels of the Sec. 3.9 example).
+ *   - Amplitudes are interleaved (re, im): complex128 = 2 doubles, complex64 = 2 floats.
+ *   - A gate acts on distinct targets t_0..t_{k-1}; its unitary U is d_T x d_T with
+ *     d_T = prod dims[t_j], row-major, each entry (re, im) as two doubles (so 2*d_T*d_T doubles).
+ *     Row/column index of U: t_0 is the most significant digit (the block layout of the
+ *     generalized CNOT, Sec. 2.1).
+ *   - Controls c_0..c_{m-1} with values v_j: the gate acts only on basis states whose digit at
+ *     c_j equals v_j, and is the identity elsewhere (Sec. 2.1 generalized CNOT and multi-controlled
+ *     Toffoli, which fire on d-1; here the value is explicit, 0 <= v_j < dims[c_j]).
+ *
+ * Ownership: every input array is copied before the call returns; the caller may free it at once.
+ * Output buffers are allocated by the caller. Handles are released with the matching *_free.
+ *
+ * Errors: every entry point returns a status (QD_OK = 0 or a negative QD_E* code) and never
+ * throws across the ABI. Arguments are validated before any device work, so a call that fails
+ * validation leaves the state bit-identical. qd_last_error() returns a message for the calling
+ * thread. Gate calls are asynchronous on the state's HIP stream; calls that return data to the host
+ * (download, probabilities to host, norm, compare) synchronise that stream and report a deferred
+ * device fault as QD_EDEVICE.
+ */
+#ifndef QD_H
+#define QD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qd_state qd_state;
+typedef struct qd_fused qd_fused;
+typedef struct qd_batch qd_batch;
+
+enum {
+  QD_OK = 0,
+  QD_EINVAL = -1,       /* malformed argument: null pointer, bad index, bad count           */
+  QD_EDIM = -2,         /* dimension mismatch: U size != d_T, radix out of range, size mismatch */
+  QD_ENOTUNITARY = -3,  /* max |U^dag U - I| > 1e-10, or a NaN/Inf entry                      */
+  QD_ENOMEM = -4,       /* device or pinned allocation failed                                */
+  QD_EOVERFLOW = -5,    /* D or its byte size overflows int64 / the device capacity           */
+  QD_EDEVICE = -6       /* a HIP call failed, or a deferred device fault was observed         */
+};
+
+enum { QD_C128 = 0, QD_C64 = 1 };                                   /* state precision */
+enum { QD_MODE_FP64_PLAIN = 0, QD_MODE_FP32_MFMA = 1, QD_MODE_BF16X3_MFMA = 2 };
+enum { QD_FLAG_SKIP_UNITARY_CHECK = 1 };
+enum { QD_GATE_X = 0, QD_GATE_Z = 1, QD_GATE_F = 2, QD_GATE_I = 3 };   /* named gates, Sec. 2.1 */
+enum { QD_CLASS_DENSE = 0, QD_CLASS_MONOMIAL = 1, QD_CLASS_DIAGONAL = 2 };
+enum { QD_ROUTE_DIRECT = 0, QD_ROUTE_TILED = 1, QD_ROUTE_DIAG = 2, QD_ROUTE_GENERIC = 3 };
+
+#define QD_MAX_QUDITS 64    /* n <= 64 */
+#define QD_MAX_RADIX 256    /* 2 <= dims[i] <= 256 */
+#define QD_MAX_GATE_DIM 1024 /* d_T <= 1024: the 4^5 x 4^5 five-ququart gate of Sec. 1 */
+#define QD_MAX_FUSED_DIM 128 /* largest fused block qd_fuse builds */
+
+/* One gate as data, for qd_fuse and the batched path. Pointers are read during the call only. */
+typedef struct {
+  int32_t k;                       /* number of targets, >= 1                                  */
+  const int32_t* targets;          /* k distinct qudit indices                                 */
+  int32_t m;                       /* number of controls, >= 0                                 */
+  const int32_t* controls;         /* m qudit indices, disjoint from targets                   */
+  const int32_t* control_values;   /* m values, 0 <= v_j < dims[c_j]                           */
+  const double* U;                 /* d_T x d_T complex, row-major, interleaved (re, im) FP64  */
+} qd_gate;
+
+/* ---------------------------------------------------------------- library, register, gates */
+
+/* Library version string (static storage). */
+const char* qd_version(void);
+
+/* Message for the last failed call on this thread (thread-local storage, valid until the next
+ * failing call on the same thread). */
+const char* qd_last_error(void);
+
+/* Register table (Sec. 2.2: the state has prod dims[i] entries). Host only, no device work.
+ * Writes D to *D_out and the n big-endian strides to strides_out[n] (caller-allocated).
+ * QD_EINVAL for n outside 1..64 or null pointers, QD_EDIM for a radix outside 2..256,
+ * QD_EOVERFLOW if D overflows int64. */
+int qd_register_strides(const int32_t* dims, int32_t n, int64_t* D_out, int64_t* strides_out);
+
+/* Unitary of a named gate of Sec. 2.1 on a wire of dimension d, written to U_out
+ * (2*d*d doubles, row-major, interleaved). Host only.
+ *   QD_GATE_X: generalized NOT X^d_{+a}, |x> -> |(x+a) mod d>, requires 1 <= a <= d-1;
+ *   QD_GATE_Z: phase-shift diag(1, w, ..., w^{d-1}), w = exp(2 pi i / d);
+ *   QD_GATE_F: generalized Hadamard (1/sqrt d) [w^{jk}];
+ *   QD_GATE_I: identity.
+ * w^m is evaluated with m reduced mod d; quarter turns are exact. QD_EINVAL for an unknown kind
+ * or a shift outside 1..d-1, QD_EDIM for d outside 2..256. */
+int qd_gate_matrix(int32_t kind, int32_t d, int32_t a, double* U_out);
+
+/* Validate one gate against a register without touching the device (the checks qd_apply_gate
+ * runs first). flags: QD_FLAG_SKIP_UNITARY_CHECK skips the unitarity test. Returns QD_OK or the
+ * code qd_apply_gate would return. */
+int qd_validate_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
+                     const int32_t* controls, const int32_t* control_values, int32_t m,
+                     const double* U, uint32_t flags);
+
+/* Structural class of a d_T x d_T unitary as the kernels see it (exact zero tests in FP64):
+ * QD_CLASS_DIAGONAL (only diagonal entries non-zero), QD_CLASS_MONOMIAL (one non-zero per row and
+ * column, e.g. X_{+a} and the qudit swap), else QD_CLASS_DENSE. Host only; -1 on bad arguments. */
+int qd_gate_class(const double* U, int32_t dT);
+
+/* Kernel family qd_apply_gate would launch for this gate on a state of register dims and
+ * precision prec, written to *route_out (host only, no device work):
+ *   QD_ROUTE_DIRECT  one slice per thread (every target stride >= the run threshold);
+ *   QD_ROUTE_TILED   slices staged in LDS (a target with a small stride);
+ *   QD_ROUTE_DIAG    elementwise phases (diagonal U);
+ *   QD_ROUTE_GENERIC any d_T up to 1024 or D >= 2^32 (U in device memory).
+ * Validation as in qd_apply_gate. */
+int qd_gate_route(const int32_t* dims, int32_t n, int32_t prec, const int32_t* targets, int32_t k,
+                  const int32_t* controls, const int32_t* control_values, int32_t m, const double* U,
+                  int32_t* route_out);
+
+/* ---------------------------------------------------------------- state vectors (Sec. 3.3) */
+
+/* Allocate a state of the register dims[0..n-1] in device memory owned by the library and set it
+ * to |0...0> (Sec. 2.2: circuits start in the computational basis state |0>; Sec. 3.2 default
+ * init_states). prec is QD_C128 or QD_C64. hip_stream is the hipStream_t every call on this state
+ * is ordered on (NULL = the null stream). *out receives the handle.
+ * QD_ENOMEM if the device allocation fails, QD_EOVERFLOW if D * bytes-per-amplitude overflows. */
+int qd_state_init(const int32_t* dims, int32_t n, int32_t prec, void* hip_stream, qd_state** out);
+
+/* As qd_state_init, but over caller-owned device memory dev_ptr of `bytes` bytes (for instance a
+ * PyTorch tensor), which must hold D amplitudes. The contents are left untouched; the library
+ * never frees this memory. QD_EDIM if bytes < D * bytes-per-amplitude. */
+int qd_state_wrap(const int32_t* dims, int32_t n, int32_t prec, void* dev_ptr, int64_t bytes,
+                  void* hip_stream, qd_state** out);
+
+/* Set the state to the basis state |values[0] ... values[n-1]> (Sec. 3.2 init_states: the
+ * Kronecker product of one basis vector per wire, Sec. 3.3 Eq. (3)). QD_EINVAL if a value is
+ * outside 0..dims[i]-1. Asynchronous. */
+int qd_state_set_basis(qd_state* s, const int32_t* values);
+
+/* Copy n = D amplitudes from host memory (interleaved, in the state's precision) into the state,
+ * or out of it into host memory. QD_EDIM if n != D. Both synchronise the stream. */
+int qd_state_upload(qd_state* s, const void* host_amps, int64_t n);
+int qd_state_download(const qd_state* s, void* host_amps, int64_t n);
+
+/* Queries: register size D, the register (dims_out needs room for 64 ints; *n_out receives n),
+ * precision, device pointer of the amplitudes. */
+int qd_state_size(const qd_state* s, int64_t* D_out);
+int qd_state_dims(const qd_state* s, int32_t* dims_out, int32_t* n_out);
+int qd_state_precision(const qd_state* s, int32_t* prec_out);
+int qd_state_device_ptr(const qd_state* s, void** ptr_out);
+
+/* Wait for all work queued on the state's stream; QD_EDEVICE reports a deferred fault. */
+int qd_state_sync(const qd_state* s);
+
+void qd_state_free(qd_state* s);
+
+/* ---------------------------------------------------------------- gate application (Sec. 2.1) */
+
+/* Apply one generalized gate in place: for every basis state whose control digits match,
+ * the amplitudes over the target digits are mixed by U (U acts as I (x) U (x) I on the register,
+ * the Kronecker-embedded Moment operator of Sec. 3.5). Covers X_{+a}, Z_d, F_d, the generalized
+ * CNOT / multi-controlled Toffoli (targets {t}, controls with values) and any user unitary
+ * (Sec. 3.4 "User Defined Gate"). Validation (before any device work): 1 <= k, k + m <= n,
+ * targets distinct and in range, controls in range, distinct and disjoint from the targets,
+ * 0 <= v_j < dims[c_j], d_T <= 1024, U unitary within 1e-10 (max-abs of U^dag U - I) with no
+ * NaN/Inf. Codes: QD_EINVAL, QD_EDIM, QD_ENOTUNITARY. A complex64 state receives U rounded to
+ * FP32. Asynchronous on the state's stream. */
+int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                  const int32_t* control_values, int32_t m, const double* U);
+
+/* qd_apply_gate with flags (QD_FLAG_SKIP_UNITARY_CHECK skips the unitarity test only). */
+int qd_apply_gate_ex(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                     const int32_t* control_values, int32_t m, const double* U, uint32_t flags);
+
+/* ---------------------------------------------------------------- gate fusion (Sec. 3.6) */
+
+/* Fusion plan, host only: groups consecutive gates greedily, in circuit order, while the union
+ * W of their targets and controls keeps prod_{w in W} dims[w] <= max_block_dim. This is the
+ * paper's "multiply the Moment operators together" (Sec. 3.6) bounded to blocks of at most
+ * max_block_dim (2 <= max_block_dim <= 128). block_of_gate[g] receives the block index of gate
+ * g (caller-allocated, g entries); *nblocks the number of blocks. A gate whose own qudits exceed
+ * max_block_dim is QD_EDIM. */
+int qd_fuse_plan(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g,
+                 int32_t max_block_dim, int32_t* block_of_gate, int32_t* nblocks);
+
+/* Plan (as qd_fuse_plan) and build every block on the GPU in FP64: block = E_last ... E_first,
+ * E_i the gate embedded in the block's window (window qudits in ascending order, the first most
+ * significant). Also emits the FP32 and split-BF16 (hi, lo) copies used by qd_apply_fused.
+ * Gates are validated as in qd_apply_gate. Asynchronous on hip_stream. */
+int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int32_t max_block_dim,
+            void* hip_stream, qd_fused** out);
+
+/* Number of blocks, and per block: window size k, window qudits (caller array of >= 16 ints),
+ * block dimension B, first gate index and gate count. */
+int qd_fused_count(const qd_fused* f, int32_t* nblocks);
+int qd_fused_block_info(const qd_fused* f, int32_t b, int32_t* k, int32_t* window, int32_t* B,
+                        int32_t* first_gate, int32_t* ngates);
+
+/* Copy block b (B x B complex FP64, row-major, interleaved) to host memory; synchronises. */
+int qd_fused_download_block(const qd_fused* f, int32_t b, double* out);
+
+/* Apply all fused blocks in order to a state whose register matches the fused circuit.
+ *   QD_MODE_FP64_PLAIN: complex128 state, FP64 blocks, FP64 arithmetic;
+ *   QD_MODE_FP32_MFMA: complex64 state, FP32 blocks on FP32 matrix cores, FP32 accumulation;
+ *   QD_MODE_BF16X3_MFMA: complex64 state, split-BF16 products a_hi b_hi + a_hi b_lo + a_lo b_hi
+ *   on BF16 matrix cores with FP32 accumulation.
+ * QD_EDIM if the register or precision does not match the mode. Asynchronous. */
+int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode);
+
+void qd_fused_free(qd_fused* f);
+
+/* ---------------------------------------------------------------- readout (Sec. 3.8) */
+
+/* Probability of every basis state, |alpha_x|^2 computed in FP64 (Sec. 3.8 OutputMethod
+ * probability; Eq. (1) normalisation). out holds D doubles; out_is_device != 0 means out is a
+ * device pointer (asynchronous), else host memory (synchronises). */
+int qd_probabilities(const qd_state* s, double* out, int32_t out_is_device);
+
+/* ||psi||^2 in FP64 by a deterministic two-pass tree reduction (same result on every run).
+ * Synchronises. */
+int qd_norm2(const qd_state* s, double* out);
+
+/* Precision diagnostics in FP64 against a complex128 reference state of the same register:
+ * max_x |psi_x - ref_x|, fidelity loss 1 - |<ref|psi>|^2 (psi unnormalised) and norm drift
+ * | ||psi||^2 - 1 |. s may be complex64 or complex128. Any output pointer may be NULL.
+ * QD_EDIM if the registers differ or ref is not complex128. Synchronises. */
+int qd_compare(const qd_state* ref64, const qd_state* s, double* max_abs, double* fid_loss,
+               double* norm_drift);
+
+/* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
+
+/* nc independent registers in one device arena: circuit c has n_per[c] qudits whose dims follow
+ * consecutively in dims_flat. All states start at |0...0>. prec is QD_C64 or QD_C128. */
+int qd_batch_create(int32_t nc, const int32_t* n_per, const int32_t* dims_flat, int32_t prec,
+                    void* hip_stream, qd_batch** out);
+
+/* Total amplitudes in the arena and the arena offset (in amplitudes) of circuit c. */
+int qd_batch_size(const qd_batch* b, int64_t* total_out);
+int qd_batch_offset(const qd_batch* b, int32_t c, int64_t* off_out);
+
+/* Reset every register to |0...0>. Asynchronous. */
+int qd_batch_reset(qd_batch* b);
+
+/* One gate layer: gate c acts on circuit c (a Moment of every circuit, Sec. 3.5). gates[c].k == 0
+ * means no gate for circuit c in this layer. Supported: one target (d_t <= 16) and at most one
+ * control; other shapes are QD_EINVAL. Every layer runs as one persistent launch. While capture
+ * is on, the launch is recorded into the batch's graph instead of being run. */
+int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
+
+/* on = 1 starts recording layers into a new graph (dropping any previous one); on = 0 ends the
+ * recording and instantiates the graph. */
+int qd_batch_capture(qd_batch* b, int32_t on);
+
+/* Launch the recorded graph once on the batch's stream. QD_EINVAL if none is recorded. */
+int qd_batch_replay(qd_batch* b);
+
+/* Copy the whole arena (total amplitudes, interleaved) to host memory; synchronises. */
+int qd_batch_download(const qd_batch* b, void* host_amps, int64_t total);
+
+void qd_batch_free(qd_batch* b);
+
+/* ---------------------------------------------------------------- tuning and calibration */
+
+/* Tile parameters the launchers use (QD_TUNE_* below): threads per workgroup (64, 128, 192 or
+ * 256), slices per thread (1, 2 or 4), amplitudes per LDS tile (power of two, 256..4096),
+ * slice columns per fused tile (32, 64, 128) and the target stride below which a gate is staged
+ * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes). 0 restores the default. Process-wide, host only;
+ * QD_EINVAL for an unknown parameter or a value outside its range. */
+enum { QD_TUNE_DIRECT_BLOCK = 0, QD_TUNE_DIRECT_SPT = 1, QD_TUNE_TILE_BLOCK = 2,
+       QD_TUNE_TILE_ELEMS = 3, QD_TUNE_DIAG_BLOCK = 4, QD_TUNE_BATCH_BLOCK = 5,
+       QD_TUNE_BATCH_SPT = 6, QD_TUNE_FUSED_COLS = 7, QD_TUNE_RUN_MIN = 8, QD_TUNE_COUNT = 9 };
+int qd_tune_set(int32_t param, int32_t value);
+int qd_tune_get(int32_t param, int32_t* value);
+
+/* Autotuner: times every candidate of the tile parameters on this state (its contents are
+ * scrambled: use a scratch state) for single-qudit gates on each qudit, keeps the fastest, and
+ * writes a JSON cache to path (NULL = no file). Synchronises. */
+int qd_autotune(qd_state* scratch, const char* path);
+
+/* Load a cache written by qd_autotune. QD_EINVAL if the file cannot be parsed. */
+int qd_tune_load(const char* path);
+
+/* Device-to-device copy of `bytes` bytes with the library's streaming copy kernel, for the HBM
+ * ceiling and the hardware-counter calibration. Asynchronous on hip_stream. */
+int qd_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QD_H */

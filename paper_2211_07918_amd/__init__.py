@@ -1,0 +1,475 @@
+"""Python binding of libqd (include/qd.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no arithmetic of its own:
+it converts NumPy arrays / Python sequences to C arrays, calls libqd, and raises QDError when the
+status is not QD_OK. Device memory and streams come from the caller (for instance PyTorch:
+``torch.cuda.current_stream().cuda_stream`` and ``tensor.data_ptr()``) as plain integers.
+
+The shared library is built in-tree by ``python -m paper_2211_07918_amd.build``; importing this
+package never builds it, and every call fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "QDError", "lib_path", "load",
+    "QD_OK", "QD_EINVAL", "QD_EDIM", "QD_ENOTUNITARY", "QD_ENOMEM", "QD_EOVERFLOW", "QD_EDEVICE",
+    "QD_C128", "QD_C64", "QD_MODE_FP64_PLAIN", "QD_MODE_FP32_MFMA", "QD_MODE_BF16X3_MFMA",
+    "QD_FLAG_SKIP_UNITARY_CHECK", "QD_GATE_X", "QD_GATE_Z", "QD_GATE_F", "QD_GATE_I",
+    "QD_CLASS_DENSE", "QD_CLASS_MONOMIAL", "QD_CLASS_DIAGONAL",
+    "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
+    "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
+    "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "qd_gate_route",
+    "qd_version", "qd_last_error", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
+    "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
+    "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
+    "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
+    "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_download_block",
+    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare",
+    "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
+    "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
+    "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_stream_copy",
+    "gate_unitary", "apply_circuit_gate", "GateArray",
+]
+
+QD_OK, QD_EINVAL, QD_EDIM, QD_ENOTUNITARY, QD_ENOMEM, QD_EOVERFLOW, QD_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+QD_C128, QD_C64 = 0, 1
+QD_MODE_FP64_PLAIN, QD_MODE_FP32_MFMA, QD_MODE_BF16X3_MFMA = 0, 1, 2
+QD_FLAG_SKIP_UNITARY_CHECK = 1
+QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
+QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2
+QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
+(QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
+ QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN) = range(9)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class QDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqd error {code}: {msg}")
+        self.code = code
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libqd.so")
+
+
+class _Gate(C.Structure):
+    _fields_ = [("k", C.c_int32), ("targets", C.POINTER(C.c_int32)), ("m", C.c_int32),
+                ("controls", C.POINTER(C.c_int32)), ("control_values", C.POINTER(C.c_int32)),
+                ("U", C.POINTER(C.c_double))]
+
+
+_P = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
+_I64P = C.POINTER(C.c_int64)
+_DP = C.POINTER(C.c_double)
+
+_SIGS = {
+    "qd_version": (C.c_char_p, []),
+    "qd_last_error": (C.c_char_p, []),
+    "qd_register_strides": (C.c_int, [_I32P, C.c_int32, _I64P, _I64P]),
+    "qd_gate_matrix": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _DP]),
+    "qd_validate_gate": (C.c_int, [_I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
+    "qd_gate_class": (C.c_int, [_DP, C.c_int32]),
+    "qd_gate_route": (C.c_int, [_I32P, C.c_int32, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, _I32P]),
+    "qd_state_init": (C.c_int, [_I32P, C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "qd_state_wrap": (C.c_int, [_I32P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.POINTER(_P)]),
+    "qd_state_set_basis": (C.c_int, [_P, _I32P]),
+    "qd_state_upload": (C.c_int, [_P, _P, C.c_int64]),
+    "qd_state_download": (C.c_int, [_P, _P, C.c_int64]),
+    "qd_state_size": (C.c_int, [_P, _I64P]),
+    "qd_state_dims": (C.c_int, [_P, _I32P, _I32P]),
+    "qd_state_precision": (C.c_int, [_P, _I32P]),
+    "qd_state_device_ptr": (C.c_int, [_P, C.POINTER(_P)]),
+    "qd_state_sync": (C.c_int, [_P]),
+    "qd_state_free": (None, [_P]),
+    "qd_apply_gate": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP]),
+    "qd_apply_gate_ex": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
+    "qd_fuse_plan": (C.c_int, [_I32P, C.c_int32, C.POINTER(_Gate), C.c_int32, C.c_int32, _I32P, _I32P]),
+    "qd_fuse": (C.c_int, [_I32P, C.c_int32, C.POINTER(_Gate), C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "qd_fused_count": (C.c_int, [_P, _I32P]),
+    "qd_fused_block_info": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I32P, _I32P, _I32P]),
+    "qd_fused_download_block": (C.c_int, [_P, C.c_int32, _DP]),
+    "qd_apply_fused": (C.c_int, [_P, _P, C.c_int32]),
+    "qd_fused_free": (None, [_P]),
+    "qd_probabilities": (C.c_int, [_P, _DP, C.c_int32]),
+    "qd_norm2": (C.c_int, [_P, _DP]),
+    "qd_compare": (C.c_int, [_P, _P, _DP, _DP, _DP]),
+    "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
+    "qd_batch_size": (C.c_int, [_P, _I64P]),
+    "qd_batch_offset": (C.c_int, [_P, C.c_int32, _I64P]),
+    "qd_batch_reset": (C.c_int, [_P]),
+    "qd_batch_apply_layer": (C.c_int, [_P, C.POINTER(_Gate)]),
+    "qd_batch_capture": (C.c_int, [_P, C.c_int32]),
+    "qd_batch_replay": (C.c_int, [_P]),
+    "qd_batch_download": (C.c_int, [_P, _P, C.c_int64]),
+    "qd_batch_free": (None, [_P]),
+    "qd_tune_set": (C.c_int, [C.c_int32, C.c_int32]),
+    "qd_tune_get": (C.c_int, [C.c_int32, _I32P]),
+    "qd_autotune": (C.c_int, [_P, C.c_char_p]),
+    "qd_tune_load": (C.c_int, [C.c_char_p]),
+    "qd_stream_copy": (C.c_int, [_P, _P, C.c_int64, _P]),
+}
+
+
+def load():
+    """Load libqd.so (built in-tree). Raises if it is missing: there is no fallback path."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise QDError(QD_EDEVICE, f"{path} is not built; run `python -m paper_2211_07918_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != QD_OK:
+        raise QDError(rc, load().qd_last_error().decode())
+
+
+def _i32(seq) -> C.Array:
+    seq = [int(v) for v in seq]
+    return (C.c_int32 * max(1, len(seq)))(*seq)
+
+
+def _cplx(U) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+# ------------------------------------------------------------------------------ library, register
+def qd_version() -> str:
+    return load().qd_version().decode()
+
+
+def qd_last_error() -> str:
+    return load().qd_last_error().decode()
+
+
+def qd_register_strides(dims: Sequence[int]):
+    D = C.c_int64()
+    st = (C.c_int64 * len(dims))()
+    _check(load().qd_register_strides(_i32(dims), len(dims), C.byref(D), st))
+    return int(D.value), [int(x) for x in st]
+
+
+def qd_gate_matrix(kind: int, d: int, a: int = 0) -> np.ndarray:
+    U = np.zeros((d, d), dtype=np.complex128)
+    _check(load().qd_gate_matrix(kind, d, a, _dptr(U)))
+    return U
+
+
+def qd_validate_gate(dims, targets, controls, control_values, U, flags: int = 0) -> int:
+    """Returns the status code (no exception): QD_OK or the error qd_apply_gate would return."""
+    Uc = _cplx(U)
+    try:
+        _check_shape(dims, targets, Uc)
+    except QDError as e:
+        return e.code
+    return int(load().qd_validate_gate(_i32(dims), len(dims), _i32(targets), len(targets), _i32(controls),
+                                       _i32(control_values), len(controls), _dptr(Uc), flags))
+
+
+def qd_gate_route(dims, prec, targets, controls, control_values, U) -> int:
+    Uc = _cplx(U)
+    _check_shape(dims, targets, Uc)
+    r = C.c_int32()
+    _check(load().qd_gate_route(_i32(dims), len(dims), prec, _i32(targets), len(targets), _i32(controls),
+                                _i32(control_values), len(controls), _dptr(Uc), C.byref(r)))
+    return int(r.value)
+
+
+def qd_gate_class(U) -> int:
+    Uc = _cplx(U)
+    return int(load().qd_gate_class(_dptr(Uc), Uc.shape[0]))
+
+
+# ------------------------------------------------------------------------------ states
+def qd_state_init(dims: Sequence[int], prec: int = QD_C128, stream: int = 0) -> int:
+    h = _P()
+    _check(load().qd_state_init(_i32(dims), len(dims), prec, _P(stream or None), C.byref(h)))
+    return h.value
+
+
+def qd_state_wrap(dims: Sequence[int], prec: int, dev_ptr: int, nbytes: int, stream: int = 0) -> int:
+    h = _P()
+    _check(load().qd_state_wrap(_i32(dims), len(dims), prec, _P(dev_ptr), nbytes, _P(stream or None), C.byref(h)))
+    return h.value
+
+
+def qd_state_set_basis(s: int, values: Sequence[int]):
+    _check(load().qd_state_set_basis(_P(s), _i32(values)))
+
+
+def _state_dtype(s: int):
+    p = C.c_int32()
+    _check(load().qd_state_precision(_P(s), C.byref(p)))
+    return np.complex128 if p.value == QD_C128 else np.complex64
+
+
+def qd_state_size(s: int) -> int:
+    D = C.c_int64()
+    _check(load().qd_state_size(_P(s), C.byref(D)))
+    return int(D.value)
+
+
+def qd_state_dims(s: int):
+    n = C.c_int32()
+    dims = (C.c_int32 * 64)()
+    _check(load().qd_state_dims(_P(s), dims, C.byref(n)))
+    return [int(x) for x in dims[:n.value]]
+
+
+def _check_shape(dims, targets, Uc):
+    if not len(targets) or any(not 0 <= int(t) < len(dims) for t in targets):
+        return  # the library reports the bad target list
+    dT = int(np.prod([dims[int(t)] for t in targets]))
+    if Uc.shape != (dT, dT):
+        raise QDError(QD_EDIM, f"U has shape {Uc.shape}, the targets need ({dT}, {dT})")
+
+
+def qd_state_precision(s: int) -> int:
+    p = C.c_int32()
+    _check(load().qd_state_precision(_P(s), C.byref(p)))
+    return int(p.value)
+
+
+def qd_state_upload(s: int, amps):
+    a = np.ascontiguousarray(np.asarray(amps, dtype=_state_dtype(s)))
+    _check(load().qd_state_upload(_P(s), a.ctypes.data_as(_P), a.size))
+
+
+def qd_state_download(s: int) -> np.ndarray:
+    out = np.empty(qd_state_size(s), dtype=_state_dtype(s))
+    _check(load().qd_state_download(_P(s), out.ctypes.data_as(_P), out.size))
+    return out
+
+
+def qd_state_device_ptr(s: int) -> int:
+    p = _P()
+    _check(load().qd_state_device_ptr(_P(s), C.byref(p)))
+    return p.value or 0
+
+
+def qd_state_sync(s: int):
+    _check(load().qd_state_sync(_P(s)))
+
+
+def qd_state_free(s: int):
+    if s:
+        load().qd_state_free(_P(s))
+
+
+# ------------------------------------------------------------------------------ gates
+def qd_apply_gate(s: int, targets, controls, control_values, U):
+    Uc = _cplx(U)
+    _check_shape(qd_state_dims(s), targets, Uc)
+    _check(load().qd_apply_gate(_P(s), _i32(targets), len(targets), _i32(controls), _i32(control_values),
+                                len(controls), _dptr(Uc)))
+
+
+def qd_apply_gate_ex(s: int, targets, controls, control_values, U, flags: int):
+    Uc = _cplx(U)
+    _check_shape(qd_state_dims(s), targets, Uc)
+    _check(load().qd_apply_gate_ex(_P(s), _i32(targets), len(targets), _i32(controls), _i32(control_values),
+                                   len(controls), _dptr(Uc), flags))
+
+
+_KIND = {"X": QD_GATE_X, "Z": QD_GATE_Z, "F": QD_GATE_F}
+
+
+def gate_unitary(gate, dims) -> np.ndarray:
+    """Unitary of a gate record (attributes kind, targets, a, U): named gates are built by
+    qd_gate_matrix from the acting wire's dimension, explicit ones are passed through."""
+    if gate.kind == "U":
+        return _cplx(gate.U)
+    return qd_gate_matrix(_KIND[gate.kind], int(dims[gate.targets[0]]), int(gate.a))
+
+
+def apply_circuit_gate(s: int, gate, dims, flags: int = 0):
+    """qd_apply_gate_ex for one gate record."""
+    qd_apply_gate_ex(s, gate.targets, gate.controls, gate.cvals, gate_unitary(gate, dims), flags)
+
+
+class GateArray:
+    """A C array of qd_gate built from gate records (keeps the referenced buffers alive)."""
+
+    def __init__(self, gates, dims_of):
+        """dims_of(i) gives the register dims of gate i (one register for qd_fuse, one per circuit
+        for the batched layer). A gate record of None is an empty slot (k = 0)."""
+        self._keep = []
+        self.arr = (_Gate * max(1, len(gates)))()
+        for i, g in enumerate(gates):
+            if g is None:
+                self.arr[i].k = 0
+                continue
+            U = gate_unitary(g, dims_of(i))
+            t, c, v = _i32(g.targets), _i32(g.controls), _i32(g.cvals)
+            self._keep += [U, t, c, v]
+            self.arr[i].k = len(g.targets)
+            self.arr[i].targets = C.cast(t, _I32P)
+            self.arr[i].m = len(g.controls)
+            self.arr[i].controls = C.cast(c, _I32P)
+            self.arr[i].control_values = C.cast(v, _I32P)
+            self.arr[i].U = _dptr(U)
+        self.n = len(gates)
+
+
+# ------------------------------------------------------------------------------ fusion
+def qd_fuse_plan(dims, gates, max_block_dim: int):
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates, lambda i: dims)
+    blk = (C.c_int32 * max(1, ga.n))()
+    nb = C.c_int32()
+    _check(load().qd_fuse_plan(_i32(dims), len(dims), ga.arr, ga.n, max_block_dim, blk, C.byref(nb)))
+    return [int(b) for b in blk[:ga.n]], int(nb.value)
+
+
+def qd_fuse(dims, gates, max_block_dim: int, stream: int = 0) -> int:
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates, lambda i: dims)
+    h = _P()
+    _check(load().qd_fuse(_i32(dims), len(dims), ga.arr, ga.n, max_block_dim, _P(stream or None), C.byref(h)))
+    return h.value
+
+
+def qd_fused_count(f: int) -> int:
+    n = C.c_int32()
+    _check(load().qd_fused_count(_P(f), C.byref(n)))
+    return int(n.value)
+
+
+def qd_fused_block_info(f: int, b: int):
+    k, B, first, ng = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    win = (C.c_int32 * 64)()
+    _check(load().qd_fused_block_info(_P(f), b, C.byref(k), win, C.byref(B), C.byref(first), C.byref(ng)))
+    return {"window": [int(x) for x in win[:k.value]], "B": int(B.value), "first_gate": int(first.value),
+            "ngates": int(ng.value)}
+
+
+def qd_fused_download_block(f: int, b: int) -> np.ndarray:
+    B = qd_fused_block_info(f, b)["B"]
+    out = np.empty((B, B), dtype=np.complex128)
+    _check(load().qd_fused_download_block(_P(f), b, _dptr(out)))
+    return out
+
+
+def qd_apply_fused(s: int, f: int, mode: int):
+    _check(load().qd_apply_fused(_P(s), _P(f), mode))
+
+
+def qd_fused_free(f: int):
+    if f:
+        load().qd_fused_free(_P(f))
+
+
+# ------------------------------------------------------------------------------ readout
+def qd_probabilities(s: int, out_dev_ptr: Optional[int] = None):
+    """FP64 probabilities: into device memory at out_dev_ptr (asynchronous), or returned as a
+    NumPy array when out_dev_ptr is None."""
+    if out_dev_ptr is not None:
+        _check(load().qd_probabilities(_P(s), C.cast(_P(out_dev_ptr), _DP), 1))
+        return None
+    out = np.empty(qd_state_size(s), dtype=np.float64)
+    _check(load().qd_probabilities(_P(s), _dptr(out), 0))
+    return out
+
+
+def qd_norm2(s: int) -> float:
+    v = C.c_double()
+    _check(load().qd_norm2(_P(s), C.byref(v)))
+    return float(v.value)
+
+
+def qd_compare(ref64: int, s: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(load().qd_compare(_P(ref64), _P(s), C.byref(a), C.byref(b), C.byref(c)))
+    return float(a.value), float(b.value), float(c.value)
+
+
+# ------------------------------------------------------------------------------ batch
+def qd_batch_create(dims_list, prec: int = QD_C64, stream: int = 0) -> int:
+    n_per = [len(d) for d in dims_list]
+    flat = [int(x) for d in dims_list for x in d]
+    h = _P()
+    _check(load().qd_batch_create(len(dims_list), _i32(n_per), _i32(flat), prec, _P(stream or None), C.byref(h)))
+    return h.value
+
+
+def qd_batch_size(b: int) -> int:
+    v = C.c_int64()
+    _check(load().qd_batch_size(_P(b), C.byref(v)))
+    return int(v.value)
+
+
+def qd_batch_offset(b: int, c: int) -> int:
+    v = C.c_int64()
+    _check(load().qd_batch_offset(_P(b), c, C.byref(v)))
+    return int(v.value)
+
+
+def qd_batch_reset(b: int):
+    _check(load().qd_batch_reset(_P(b)))
+
+
+def qd_batch_apply_layer(b: int, gates):
+    """gates: a GateArray with one slot per circuit."""
+    _check(load().qd_batch_apply_layer(_P(b), gates.arr))
+
+
+def qd_batch_capture(b: int, on: bool):
+    _check(load().qd_batch_capture(_P(b), 1 if on else 0))
+
+
+def qd_batch_replay(b: int):
+    _check(load().qd_batch_replay(_P(b)))
+
+
+def qd_batch_download(b: int, dtype=np.complex64) -> np.ndarray:
+    out = np.empty(qd_batch_size(b), dtype=dtype)
+    _check(load().qd_batch_download(_P(b), out.ctypes.data_as(_P), out.size))
+    return out
+
+
+def qd_batch_free(b: int):
+    if b:
+        load().qd_batch_free(_P(b))
+
+
+# ------------------------------------------------------------------------------ tuning, calibration
+def qd_tune_set(param: int, value: int):
+    _check(load().qd_tune_set(param, value))
+
+
+def qd_tune_get(param: int) -> int:
+    v = C.c_int32()
+    _check(load().qd_tune_get(param, C.byref(v)))
+    return int(v.value)
+
+
+def qd_autotune(scratch_state: int, path: Optional[str] = None):
+    _check(load().qd_autotune(_P(scratch_state), path.encode() if path else None))
+
+
+def qd_tune_load(path: str):
+    _check(load().qd_tune_load(path.encode()))
+
+
+def qd_stream_copy(dst: int, src: int, nbytes: int, stream: int = 0):
+    _check(load().qd_stream_copy(_P(dst), _P(src), nbytes, _P(stream or None)))

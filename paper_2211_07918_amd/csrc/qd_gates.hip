@@ -1,0 +1,607 @@
+// Gate-application kernels for gfx950 and their launcher.
+//
+// One generalized gate (Sec. 2.1) applied in place: every slice of the register (the d_T
+// amplitudes that share all non-target digits) whose control digits match is multiplied by U.
+// That is the Kronecker-embedded Moment operator I (x) U (x) I of Sec. 3.5 applied to the state
+// vector, at O(D d_T) cost.
+//
+// Kernel families (each HBM-bound: at most 8 d_T flops per 2 x 16 bytes moved):
+//   k_slices_direct  one slice per thread. Used when every target has a stride >= run_min, so the
+//                    lanes of a wavefront take consecutive low digits and each load instruction
+//                    reads one contiguous run.
+//   k_slices_tiled   a low-stride target: the workgroup stages a tile of whole slices in LDS with
+//                    contiguous coalesced loads (runs of the low suffix of the register), mixes
+//                    each slice inside LDS and writes the tile back coalesced.
+//   k_diag           diagonal gates (Z_d, controlled phases): elementwise, consecutive lanes on
+//                    consecutive amplitudes whatever the target strides.
+//   k_dense_generic  any d_T <= 1024 and any register size (64-bit indices): slices gathered into
+//                    LDS, U read from device memory.
+// The slice kernels take U (dense) or a destination/phase table (monomial: X_{+a}, controlled
+// shifts, qudit swaps) inside the kernel arguments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "qd_internal.h"
+
+namespace qd {
+
+template <typename R> struct CxT;
+template <> struct CxT<double> { using T = double2; };
+template <> struct CxT<float> { using T = float2; };
+
+// ------------------------------------------------------------------------------------------ index maps
+__device__ __forceinline__ int64_t sm_offset(const SliceMap& sm, uint32_t idx) {
+  int64_t off = sm.base;
+  uint32_t rem = idx;
+#pragma unroll
+  for (int g = 0; g < kMaxGroups; ++g) {
+    if (g < int(sm.ng)) {
+      const uint32_t q = (g + 1 < int(sm.ng)) ? magic_div(rem, sm.gmag[g]) : 0u;
+      const uint32_t r = rem - q * sm.gdim[g];
+      off += int64_t(r) * sm.gstride[g];
+      rem = q;
+    }
+  }
+  return off;
+}
+
+__device__ __forceinline__ int64_t sm_offset_loc(const SliceMap& sm, uint32_t idx, uint32_t* loc) {
+  int64_t off = sm.base;
+  uint32_t rem = idx, l = 0;
+#pragma unroll
+  for (int g = 0; g < kMaxGroups; ++g) {
+    if (g < int(sm.ng)) {
+      const uint32_t q = (g + 1 < int(sm.ng)) ? magic_div(rem, sm.gmag[g]) : 0u;
+      const uint32_t r = rem - q * sm.gdim[g];
+      off += int64_t(r) * sm.gstride[g];
+      l += r * sm.lmul[g];
+      rem = q;
+    }
+  }
+  *loc = l;
+  return off;
+}
+
+__device__ __forceinline__ int64_t sm64_offset(const SliceMap64& sm, uint64_t idx) {
+  int64_t off = sm.base;
+  uint64_t rem = idx;
+  for (uint32_t g = 0; g < sm.ng; ++g) {
+    const uint64_t q = rem / sm.gdim[g];
+    off += int64_t(rem - q * sm.gdim[g]) * sm.gstride[g];
+    rem = q;
+  }
+  return off;
+}
+
+// ------------------------------------------------------------------------------------------ gate ops
+template <typename R, int DT> struct DenseOp { R u[2 * DT * DT]; };
+template <typename R, int DT> struct MonoOp { R ph[2 * DT]; int32_t dst[DT]; };
+
+// doff[c] = toff[dst[c]] for monomial gates (filled by the host so no kernel indexes its
+// arguments with a run-time value); unused by dense gates.
+
+template <typename C, typename R, int DT, typename P>
+__device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t* toff, const int64_t*,
+                                          const DenseOp<R, DT>& op, const C (&x)[DT]) {
+#pragma unroll
+  for (int r = 0; r < DT; ++r) {
+    R re = R(0), im = R(0);
+#pragma unroll
+    for (int c = 0; c < DT; ++c) {
+      const R ur = op.u[2 * (r * DT + c)], ui = op.u[2 * (r * DT + c) + 1];
+      re = fma(ur, x[c].x, re);
+      re = fma(-ui, x[c].y, re);
+      im = fma(ur, x[c].y, im);
+      im = fma(ui, x[c].x, im);
+    }
+    C y;
+    y.x = re;
+    y.y = im;
+    p[base + toff[r]] = y;
+  }
+}
+
+template <typename C, typename R, int DT, typename P>
+__device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t*, const int64_t* doff,
+                                          const MonoOp<R, DT>& op, const C (&x)[DT]) {
+#pragma unroll
+  for (int c = 0; c < DT; ++c) {
+    const R pr = op.ph[2 * c], pi = op.ph[2 * c + 1];
+    C y;
+    y.x = fma(pr, x[c].x, -pi * x[c].y);
+    y.y = fma(pr, x[c].y, pi * x[c].x);
+    p[base + doff[c]] = y;
+  }
+}
+
+// ------------------------------------------------------------------------------------------ direct
+template <typename R, int DT, typename OP>
+struct DirectArgs {
+  R* psi;
+  SliceMap sm;
+  int64_t toff[DT];
+  int64_t doff[DT];
+  OP op;
+};
+
+template <typename R, int DT, typename OP, int SPT>
+__global__ __launch_bounds__(256) void k_slices_direct(DirectArgs<R, DT, OP> a) {
+  using C = typename CxT<R>::T;
+  C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
+  const uint64_t bs = blockDim.x;
+  const uint64_t first = uint64_t(blockIdx.x) * bs * SPT + threadIdx.x;
+  int64_t base[SPT];
+  C x[SPT][DT];
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const uint64_t i = first + s * bs;
+    base[s] = i < a.sm.count ? sm_offset(a.sm, uint32_t(i)) : -1;
+  }
+#pragma unroll
+  for (int s = 0; s < SPT; ++s)
+    if (base[s] >= 0) {
+#pragma unroll
+      for (int y = 0; y < DT; ++y) x[s][y] = psi[base[s] + a.toff[y]];
+    }
+#pragma unroll
+  for (int s = 0; s < SPT; ++s)
+    if (base[s] >= 0) mix_store<C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
+}
+
+// ------------------------------------------------------------------------------------------ tiled
+template <typename R, int DT, typename OP>
+struct TileArgs {
+  R* psi;
+  SliceMap tiles;                 // tile index -> global offset of the tile's origin
+  SliceMap inner;                 // slice index inside a tile -> LDS index of its y = 0 amplitude
+  uint32_t BL;                    // run length (amplitudes of the low suffix)
+  uint32_t dH;                    // number of runs (product of the high targets' dims)
+  int64_t hoff[kMaxTileRuns];     // global offset of run h from the tile origin
+  int64_t toff[DT];               // LDS offset of target combination y
+  int64_t doff[DT];               // monomial: LDS offset of the row column y moves to
+  OP op;
+};
+
+template <typename R, int DT, typename OP>
+__global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
+  using C = typename CxT<R>::T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
+  const uint32_t bs = blockDim.x, tid = threadIdx.x;
+  for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
+    const int64_t g0 = sm_offset(a.tiles, tile);
+#pragma unroll
+    for (int h = 0; h < kMaxTileRuns; ++h) {
+      if (h < int(a.dH)) {
+        const C* src = psi + g0 + a.hoff[h];
+        C* dst = lds + h * a.BL;
+        for (uint32_t l = tid; l < a.BL; l += bs) dst[l] = src[l];
+      }
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < a.inner.count; j += bs) {
+      const int64_t b = sm_offset(a.inner, j);
+      C x[DT];
+#pragma unroll
+      for (int y = 0; y < DT; ++y) x[y] = lds[b + a.toff[y]];
+      mix_store<C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < kMaxTileRuns; ++h) {
+      if (h < int(a.dH)) {
+        C* dst = psi + g0 + a.hoff[h];
+        const C* src = lds + h * a.BL;
+        for (uint32_t l = tid; l < a.BL; l += bs) dst[l] = src[l];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------ diagonal
+template <typename R>
+struct DiagArgs {
+  R* psi;
+  SliceMap sm;                     // over all non-control qudits; targets are singleton groups
+  R ph[2 * kMaxInlineTable];       // phase of target combination loc
+};
+
+template <typename R, int SPT>
+__global__ __launch_bounds__(256) void k_diag(DiagArgs<R> a) {
+  using C = typename CxT<R>::T;
+  C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
+  const uint64_t bs = blockDim.x;
+  const uint64_t first = uint64_t(blockIdx.x) * bs * SPT + threadIdx.x;
+  int64_t off[SPT];
+  uint32_t loc[SPT];
+  C x[SPT];
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const uint64_t i = first + s * bs;
+    off[s] = i < a.sm.count ? sm_offset_loc(a.sm, uint32_t(i), &loc[s]) : -1;
+  }
+#pragma unroll
+  for (int s = 0; s < SPT; ++s)
+    if (off[s] >= 0) x[s] = psi[off[s]];
+#pragma unroll
+  for (int s = 0; s < SPT; ++s)
+    if (off[s] >= 0) {
+      const R pr = a.ph[2 * loc[s]], pi = a.ph[2 * loc[s] + 1];
+      C y;
+      y.x = fma(pr, x[s].x, -pi * x[s].y);
+      y.y = fma(pr, x[s].y, pi * x[s].x);
+      psi[off[s]] = y;
+    }
+}
+
+// ------------------------------------------------------------------------------------------ generic
+struct GenericHead {
+  SliceMap64 sm;
+  int32_t dT;
+  int32_t nsw;        // slices per workgroup iteration
+  // followed by int64_t toff[dT] and then 2 dT^2 values of R (U, row-major interleaved)
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigned char* desc) {
+  using C = typename CxT<R>::T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  C* xs = reinterpret_cast<C*>(lds_raw);
+  const GenericHead& h = *reinterpret_cast<const GenericHead*>(desc);
+  const int64_t* toff = reinterpret_cast<const int64_t*>(desc + sizeof(GenericHead));
+  const R* U = reinterpret_cast<const R*>(desc + sizeof(GenericHead) + sizeof(int64_t) * h.dT);
+  C* psi = reinterpret_cast<C*>(psi_raw);
+  const uint32_t dT = uint32_t(h.dT), nsw = uint32_t(h.nsw), tot = dT * nsw;
+  for (uint64_t s0 = uint64_t(blockIdx.x) * nsw; s0 < h.sm.count; s0 += uint64_t(gridDim.x) * nsw) {
+    for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
+      const uint32_t j = e / dT, y = e - j * dT;
+      if (s0 + j < h.sm.count) xs[e] = psi[sm64_offset(h.sm, s0 + j) + toff[y]];
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
+      const uint32_t j = e / dT, row = e - j * dT;
+      if (s0 + j >= h.sm.count) continue;
+      R re = R(0), im = R(0);
+      const R* u = U + 2 * size_t(row) * dT;
+      const C* x = xs + j * dT;
+      for (uint32_t c = 0; c < dT; ++c) {
+        re = fma(u[2 * c], x[c].x, re);
+        re = fma(-u[2 * c + 1], x[c].y, re);
+        im = fma(u[2 * c], x[c].y, im);
+        im = fma(u[2 * c + 1], x[c].x, im);
+      }
+      C y;
+      y.x = re;
+      y.y = im;
+      psi[sm64_offset(h.sm, s0 + j) + toff[row]] = y;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------ utility kernels
+template <typename R>
+__global__ __launch_bounds__(256) void k_fill_basis(R* psi_raw, uint64_t D, uint64_t idx) {
+  using C = typename CxT<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_raw);
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
+    C v;
+    v.x = i == idx ? R(1) : R(0);
+    v.y = R(0);
+    psi[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += uint64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------------------------------ launch helpers
+static inline unsigned grid_for(uint64_t items, uint64_t per_block) {
+  const uint64_t g = (items + per_block - 1) / per_block;
+  return unsigned(std::max<uint64_t>(1, g));
+}
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return QD_OK;
+}
+
+// target offsets: y in mixed radix over the targets in listed order, t_0 most significant
+static void target_offsets(const Register& r, const GatePlan& p, int64_t* toff) {
+  for (int y = 0; y < p.dT; ++y) {
+    int rem = y;
+    int64_t off = 0;
+    for (int j = p.k - 1; j >= 0; --j) {
+      const int d = r.dims[p.targets[j]];
+      off += int64_t(rem % d) * r.strides[p.targets[j]];
+      rem /= d;
+    }
+    toff[y] = off;
+  }
+}
+
+template <typename R, int DT>
+static void fill_dense(const GatePlan& p, DenseOp<R, DT>* op) {
+  for (int i = 0; i < 2 * DT * DT; ++i) op->u[i] = R(p.U[i]);
+}
+template <typename R, int DT>
+static void fill_mono(const GatePlan& p, MonoOp<R, DT>* op) {
+  for (int i = 0; i < DT; ++i) {
+    op->dst[i] = p.dst[i];
+    op->ph[2 * i] = R(p.ph[2 * i]);
+    op->ph[2 * i + 1] = R(p.ph[2 * i + 1]);
+  }
+}
+
+// LDS tile geometry: the low suffix L = {pq, ..., n-1} of the register holds every target whose
+// stride is below run_min and is grown towards longer contiguous runs (>= 256 amplitudes) while
+// the tile (dH runs of BL amplitudes) fits the LDS budget. Returns false when no target is low
+// (the direct kernel applies) or the tile would not fit.
+bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) {
+  const TuneParams& tp = tune();
+  int low_idx = r.n;
+  for (int j = 0; j < p.k; ++j)
+    if (r.strides[p.targets[j]] < tp.run_min) low_idx = std::min(low_idx, int(p.targets[j]));
+  if (low_idx >= r.n) return false;
+  const uint64_t emax = uint64_t(tp.tile_elems) * (prec == QD_C128 ? 1u : 2u);
+  const uint64_t run_target = 256;
+  bool is_t[QD_MAX_QUDITS] = {};
+  for (int j = 0; j < p.k; ++j) is_t[p.targets[j]] = true;
+  int pq = low_idx;
+  uint64_t BL = uint64_t(r.strides[pq]) * r.dims[pq];
+  uint64_t dH = 1;
+  for (int i = 0; i < pq; ++i)
+    if (is_t[i]) dH *= r.dims[i];
+  while (pq > 0 && BL < run_target) {
+    const int q = pq - 1;
+    const uint64_t nBL = BL * r.dims[q];
+    const uint64_t ndH = is_t[q] ? dH / r.dims[q] : dH;
+    if (nBL * ndH > emax) break;
+    pq = q;
+    BL = nBL;
+    dH = ndH;
+  }
+  if (dH > uint64_t(kMaxTileRuns) || BL * dH > emax) return false;
+  g->pq = pq;
+  g->BL = BL;
+  g->dH = dH;
+  return true;
+}
+
+int route_gate(const Register& r, int prec, const GatePlan& p) {
+  const bool fast = uint64_t(r.D) <= 0xFFFFFFFFull;
+  if (!fast) return QD_ROUTE_GENERIC;
+  if (p.cls == QD_CLASS_DIAGONAL && p.dT <= kMaxInlineTable) return QD_ROUTE_DIAG;
+  const bool mono = p.cls == QD_CLASS_MONOMIAL &&
+                    (p.dT <= 9 || p.dT == 12 || p.dT == 16);
+  const bool dense = p.cls != QD_CLASS_DIAGONAL && p.dT <= kMaxInlineDense;
+  if (!mono && !dense) return QD_ROUTE_GENERIC;
+  TileGeom g;
+  return tile_geometry(r, p, prec, &g) ? QD_ROUTE_TILED : QD_ROUTE_DIRECT;
+}
+
+template <int DT>
+static void fill_doff(const GatePlan& p, const int64_t* toff, int64_t* doff) {
+  for (int c = 0; c < DT; ++c) doff[c] = p.dst.empty() ? 0 : toff[p.dst[c]];
+}
+
+template <typename R, int DT, typename OP>
+static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
+  const Register& r = s->reg;
+  const TuneParams& tp = tune();
+  int role[QD_MAX_QUDITS] = {};
+  for (int j = 0; j < p.k; ++j) role[p.targets[j]] = 1;
+  for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
+
+  TileGeom tg;
+  if (tile_geometry(r, p, sizeof(R) == 8 ? QD_C128 : QD_C64, &tg)) {
+    const int pq = tg.pq;
+    const uint64_t BL = tg.BL, dH = tg.dH;
+    {
+      TileArgs<R, DT, OP> a;
+      std::memset(&a, 0, sizeof(a));
+      a.psi = reinterpret_cast<R*>(s->data);
+      a.op = op;
+      a.BL = uint32_t(BL);
+      a.dH = uint32_t(dH);
+      int64_t tbase = 0, ibase = 0;
+      for (int j = 0; j < p.m; ++j) {
+        const int c = p.controls[j];
+        if (c < pq) tbase += int64_t(p.cvals[j]) * r.strides[c];
+        else ibase += int64_t(p.cvals[j]) * r.strides[c];
+      }
+      int rc = fill_slicemap(make_groups(r, role, nullptr, 0, pq), tbase, &a.tiles);
+      if (rc) return rc;
+      rc = fill_slicemap(make_groups(r, role, nullptr, pq, r.n), ibase, &a.inner);
+      if (rc) return rc;
+      // run offsets: h in mixed radix over the high targets in listed order
+      int hmul[QD_MAX_QUDITS] = {};
+      {
+        int m = 1;
+        for (int j = p.k - 1; j >= 0; --j)
+          if (p.targets[j] < pq) {
+            hmul[j] = m;
+            m *= r.dims[p.targets[j]];
+          }
+      }
+      for (uint32_t h = 0; h < a.dH; ++h) {
+        int64_t off = 0;
+        for (int j = 0; j < p.k; ++j)
+          if (p.targets[j] < pq) off += int64_t((h / hmul[j]) % r.dims[p.targets[j]]) * r.strides[p.targets[j]];
+        a.hoff[h] = off;
+      }
+      for (int y = 0; y < DT; ++y) {
+        int rem = y;
+        int64_t off = 0;
+        for (int j = p.k - 1; j >= 0; --j) {
+          const int t = p.targets[j];
+          const int dg = rem % r.dims[t];
+          rem /= r.dims[t];
+          off += t < pq ? int64_t(dg) * hmul[j] * int64_t(BL) : int64_t(dg) * r.strides[t];
+        }
+        a.toff[y] = off;
+      }
+      fill_doff<DT>(p, a.toff, a.doff);
+      if (a.tiles.count == 0 || a.inner.count == 0) return QD_OK;
+      const size_t lds = size_t(BL * dH) * sizeof(R) * 2;
+      const unsigned grid = a.tiles.count;
+      hipLaunchKernelGGL((k_slices_tiled<R, DT, OP>), dim3(grid), dim3(tp.tile_block), lds, s->stream, a);
+      return check_launch("k_slices_tiled");
+    }
+  }
+
+  // ---- direct: one slice per thread
+  DirectArgs<R, DT, OP> a;
+  std::memset(&a, 0, sizeof(a));
+  a.psi = reinterpret_cast<R*>(s->data);
+  a.op = op;
+  int64_t base = 0;
+  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  int rc = fill_slicemap(make_groups(r, role, nullptr, 0, r.n), base, &a.sm);
+  if (rc) return rc;
+  target_offsets(r, p, a.toff);
+  fill_doff<DT>(p, a.toff, a.doff);
+  if (a.sm.count == 0) return QD_OK;
+  const int bs = tp.direct_block;
+  if (tp.direct_spt >= 2) {
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
+  } else {
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0, s->stream, a);
+  }
+  return check_launch("k_slices_direct");
+}
+
+template <typename R, int DT>
+static int launch_dense_t(qd_state* s, const GatePlan& p) {
+  DenseOp<R, DT> op;
+  fill_dense<R, DT>(p, &op);
+  return launch_slices<R, DT>(s, p, op);
+}
+
+template <typename R, int DT>
+static int launch_mono_t(qd_state* s, const GatePlan& p) {
+  MonoOp<R, DT> op;
+  fill_mono<R, DT>(p, &op);
+  return launch_slices<R, DT>(s, p, op);
+}
+
+template <typename R>
+static int launch_diag(qd_state* s, const GatePlan& p) {
+  const Register& r = s->reg;
+  int role[QD_MAX_QUDITS] = {};
+  uint32_t lmul[QD_MAX_QUDITS] = {};
+  uint32_t m = 1;
+  for (int j = p.k - 1; j >= 0; --j) {
+    role[p.targets[j]] = 2;
+    lmul[p.targets[j]] = m;
+    m *= uint32_t(r.dims[p.targets[j]]);
+  }
+  for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
+  DiagArgs<R> a;
+  std::memset(&a, 0, sizeof(a));
+  a.psi = reinterpret_cast<R*>(s->data);
+  int64_t base = 0;
+  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  int rc = fill_slicemap(make_groups(r, role, lmul, 0, r.n), base, &a.sm);
+  if (rc) return rc;
+  for (int i = 0; i < 2 * p.dT; ++i) a.ph[i] = R(p.ph[i]);
+  if (a.sm.count == 0) return QD_OK;
+  const int bs = tune().diag_block;
+  hipLaunchKernelGGL((k_diag<R, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
+  return check_launch("k_diag");
+}
+
+template <typename R>
+static int launch_generic(qd_state* s, const GatePlan& p) {
+  const Register& r = s->reg;
+  int role[QD_MAX_QUDITS] = {};
+  for (int j = 0; j < p.k; ++j) role[p.targets[j]] = 1;
+  for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
+  int64_t base = 0;
+  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  const size_t bytes = sizeof(GenericHead) + sizeof(int64_t) * p.dT + sizeof(R) * 2 * size_t(p.dT) * p.dT;
+  std::vector<unsigned char> buf(bytes, 0);
+  auto* h = reinterpret_cast<GenericHead*>(buf.data());
+  fill_slicemap64(make_groups(r, role, nullptr, 0, r.n), base, &h->sm);
+  h->dT = p.dT;
+  h->nsw = std::max(1, 1024 / p.dT);
+  target_offsets(r, p, reinterpret_cast<int64_t*>(buf.data() + sizeof(GenericHead)));
+  R* U = reinterpret_cast<R*>(buf.data() + sizeof(GenericHead) + sizeof(int64_t) * p.dT);
+  for (size_t i = 0; i < 2 * size_t(p.dT) * p.dT; ++i) U[i] = R(p.U[i]);
+  if (h->sm.count == 0) return QD_OK;
+  void* dev = nullptr;
+  int rc = ring_push(s, buf.data(), bytes, &dev);
+  if (rc) return rc;
+  const uint64_t iters = (h->sm.count + h->nsw - 1) / h->nsw;
+  const unsigned grid = unsigned(std::min<uint64_t>(iters, 65536));
+  const size_t lds = size_t(h->nsw) * p.dT * sizeof(R) * 2;
+  hipLaunchKernelGGL((k_dense_generic<R>), dim3(grid), dim3(256), lds, s->stream, reinterpret_cast<R*>(s->data),
+                     static_cast<const unsigned char*>(dev));
+  return check_launch("k_dense_generic");
+}
+
+template <typename R>
+static int launch_gate_t(qd_state* s, const GatePlan& p) {
+  const int route = route_gate(s->reg, s->prec, p);
+  if (route == QD_ROUTE_GENERIC) return launch_generic<R>(s, p);
+  if (route == QD_ROUTE_DIAG) return launch_diag<R>(s, p);
+  if (p.cls == QD_CLASS_MONOMIAL) {
+    switch (p.dT) {
+      case 2: return launch_mono_t<R, 2>(s, p);
+      case 3: return launch_mono_t<R, 3>(s, p);
+      case 4: return launch_mono_t<R, 4>(s, p);
+      case 5: return launch_mono_t<R, 5>(s, p);
+      case 6: return launch_mono_t<R, 6>(s, p);
+      case 7: return launch_mono_t<R, 7>(s, p);
+      case 8: return launch_mono_t<R, 8>(s, p);
+      case 9: return launch_mono_t<R, 9>(s, p);
+      case 12: return launch_mono_t<R, 12>(s, p);
+      case 16: return launch_mono_t<R, 16>(s, p);
+      default: break;
+    }
+  }
+  switch (p.dT) {
+    case 2: return launch_dense_t<R, 2>(s, p);
+    case 3: return launch_dense_t<R, 3>(s, p);
+    case 4: return launch_dense_t<R, 4>(s, p);
+    case 5: return launch_dense_t<R, 5>(s, p);
+    case 6: return launch_dense_t<R, 6>(s, p);
+    case 7: return launch_dense_t<R, 7>(s, p);
+    case 8: return launch_dense_t<R, 8>(s, p);
+    case 9: return launch_dense_t<R, 9>(s, p);
+    default: return launch_generic<R>(s, p);
+  }
+}
+
+int launch_gate(qd_state* s, const GatePlan& p) {
+  return s->prec == QD_C128 ? launch_gate_t<double>(s, p) : launch_gate_t<float>(s, p);
+}
+
+int launch_fill_basis(qd_state* s, int64_t index) {
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned grid = unsigned(std::min<uint64_t>((D + 255) / 256, 65536));
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_fill_basis<double>), dim3(grid), dim3(256), 0, s->stream, reinterpret_cast<double*>(s->data), D, uint64_t(index));
+  else
+    hipLaunchKernelGGL((k_fill_basis<float>), dim3(grid), dim3(256), 0, s->stream, reinterpret_cast<float*>(s->data), D, uint64_t(index));
+  return check_launch("k_fill_basis");
+}
+
+int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
+  const uint64_t n16 = uint64_t(bytes) / 16;
+  if (n16 == 0) return QD_OK;
+  const unsigned grid = unsigned(std::min<uint64_t>((n16 + 255) / 256, 1u << 20));
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint4*>(dst),
+                     reinterpret_cast<const uint4*>(src), n16);
+  return check_launch("k_stream_copy");
+}
+
+}  // namespace qd

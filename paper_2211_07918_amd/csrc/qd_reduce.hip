@@ -1,0 +1,168 @@
+// Readout kernels (Sec. 3.8): probabilities |alpha_x|^2 in FP64, the squared norm, and the
+// precision diagnostics of a state against a complex128 reference. All sums are deterministic:
+// a fixed grid (a function of D only) reduces fixed strided subsets in a fixed tree order, then a
+// single workgroup reduces the partials in a fixed order, so reruns are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "qd_internal.h"
+
+namespace qd {
+
+constexpr int kRedBlock = 256;
+constexpr int kRedMaxGrid = 2048;
+
+template <typename R> struct CxR;
+template <> struct CxR<double> { using T = double2; };
+template <> struct CxR<float> { using T = float2; };
+
+static unsigned red_grid(uint64_t D) {
+  return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(kRedMaxGrid, (D + kRedBlock * 8 - 1) / (kRedBlock * 8))));
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_probabilities(const R* psi_raw, double* __restrict__ p, uint64_t D) {
+  using C = typename CxR<R>::T;
+  const C* psi = reinterpret_cast<const C*>(psi_raw);
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
+    const C a = psi[i];
+    const double re = double(a.x), im = double(a.y);
+    p[i] = re * re + im * im;
+  }
+}
+
+// NV values per thread, reduced by sum (slot < NSUM) or max (other slots)
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], int nsum, double* out) {
+  __shared__ double sh[NV][kRedBlock];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double a = sh[q][threadIdx.x], b = sh[q][threadIdx.x + w];
+        sh[q][threadIdx.x] = q < nsum ? a + b : fmax(a, b);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = sh[q][0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_norm_partial(const R* psi_raw, uint64_t D, double* partial) {
+  using C = typename CxR<R>::T;
+  const C* psi = reinterpret_cast<const C*>(psi_raw);
+  double v[1] = {0.0};
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
+    const C a = psi[i];
+    const double re = double(a.x), im = double(a.y);
+    v[0] += re * re + im * im;
+  }
+  block_reduce<1>(v, 1, partial + blockIdx.x);
+}
+
+// slots: 0 Re<ref|s>, 1 Im<ref|s>, 2 ||s||^2, 3 max |s - ref|
+template <typename R>
+__global__ __launch_bounds__(256) void k_compare_partial(const double* ref_raw, const R* s_raw, uint64_t D, double* partial) {
+  using C = typename CxR<R>::T;
+  const double2* ref = reinterpret_cast<const double2*>(ref_raw);
+  const C* s = reinterpret_cast<const C*>(s_raw);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
+    const double2 a = ref[i];
+    const C b = s[i];
+    const double br = double(b.x), bi = double(b.y);
+    v[0] += a.x * br + a.y * bi;   // conj(a) * b
+    v[1] += a.x * bi - a.y * br;
+    v[2] += br * br + bi * bi;
+    const double dr = br - a.x, di = bi - a.y;
+    v[3] = fmax(v[3], sqrt(dr * dr + di * di));
+  }
+  double* out = partial + 4 * size_t(blockIdx.x);
+  block_reduce<4>(v, 3, out);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_finish(const double* partial, unsigned n, int nsum, double* out) {
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = 0.0;
+  for (unsigned i = threadIdx.x; i < n; i += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double x = partial[size_t(i) * NV + q];
+      v[q] = q < nsum ? v[q] + x : fmax(v[q], x);
+    }
+  block_reduce<NV>(v, nsum, out);
+}
+
+static int ensure_red(qd_state* s, size_t doubles) {
+  if (s->red_cap >= doubles) return QD_OK;
+  if (s->red) (void)hipFree(s->red);
+  s->red = nullptr;
+  s->red_cap = 0;
+  QD_HIP(hipMalloc((void**)&s->red, doubles * sizeof(double)));
+  s->red_cap = doubles;
+  return QD_OK;
+}
+
+int launch_probabilities(const qd_state* s, double* out_dev) {
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned grid = unsigned(std::min<uint64_t>((D + 255) / 256, 1u << 16));
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_probabilities<double>), dim3(grid), dim3(256), 0, s->stream, (const double*)s->data, out_dev, D);
+  else
+    hipLaunchKernelGGL((k_probabilities<float>), dim3(grid), dim3(256), 0, s->stream, (const float*)s->data, out_dev, D);
+  QD_HIP(hipGetLastError());
+  return QD_OK;
+}
+
+int reduce_norm2(const qd_state* cs, double* out) {
+  qd_state* s = const_cast<qd_state*>(cs);
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned g = red_grid(D);
+  int rc = ensure_red(s, g + 8);
+  if (rc) return rc;
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_norm_partial<double>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)s->data, D, s->red);
+  else
+    hipLaunchKernelGGL((k_norm_partial<float>), dim3(g), dim3(kRedBlock), 0, s->stream, (const float*)s->data, D, s->red);
+  hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(kRedBlock), 0, s->stream, s->red, g, 1, s->red + g);
+  QD_HIP(hipGetLastError());
+  QD_HIP(hipMemcpyAsync(out, s->red + g, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QD_HIP(hipStreamSynchronize(s->stream));
+  return QD_OK;
+}
+
+int reduce_compare(const qd_state* ref, const qd_state* cs, double* max_abs, double* fid, double* drift) {
+  qd_state* s = const_cast<qd_state*>(cs);
+  // the reference must be complete before s's stream reads it
+  if (ref->stream != s->stream) QD_HIP(hipStreamSynchronize(ref->stream));
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned g = red_grid(D);
+  int rc = ensure_red(s, 4 * size_t(g) + 8);
+  if (rc) return rc;
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_compare_partial<double>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)ref->data,
+                       (const double*)s->data, D, s->red);
+  else
+    hipLaunchKernelGGL((k_compare_partial<float>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)ref->data,
+                       (const float*)s->data, D, s->red);
+  hipLaunchKernelGGL((k_finish<4>), dim3(1), dim3(kRedBlock), 0, s->stream, s->red, g, 3, s->red + 4 * size_t(g));
+  QD_HIP(hipGetLastError());
+  double h[4];
+  QD_HIP(hipMemcpyAsync(h, s->red + 4 * size_t(g), 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QD_HIP(hipStreamSynchronize(s->stream));
+  if (max_abs) *max_abs = h[3];
+  if (fid) *fid = 1.0 - (h[0] * h[0] + h[1] * h[1]);
+  if (drift) *drift = std::fabs(h[2] - 1.0);
+  return QD_OK;
+}
+
+}  // namespace qd

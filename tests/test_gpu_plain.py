@@ -1,0 +1,370 @@
+"""GPU parity of the plain gate path (qd_apply_gate) against the oracle, through the C ABI.
+
+Tolerances:
+  * complex128: max-abs amplitude error <= 1e-12 (the bound the method is held to);
+  * complex64: each gate adds at most ~ c d_T 2^-24 to the 2-norm error of a unit state (U and
+    the state rounded to FP32, d_T products summed with fused multiply-adds), so G gates stay
+    below 4 G d_T,max 2^-24 in the 2-norm and therefore in max-abs; fidelity loss <= 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+import paper_2211_07918_amd as Q
+from gpu_util import fidelity_loss, max_abs, run_gpu, torch_stream
+
+pytestmark = pytest.mark.gpu
+
+U24 = 2.0 ** -24
+
+
+def c64_tol(ngates, dmax):
+    return 4.0 * ngates * dmax * U24
+
+
+@pytest.fixture(scope="module")
+def stream():
+    return torch_stream()
+
+
+# ------------------------------------------------------------------------------ paper example
+def test_worked_example_bit_exact(stream):
+    """Sec. 3.9 worked example: exactly 0.7071067811865475 at |000> and |120>."""
+    circ = C.Circuit((2, 3, 3), [C.Gate("F", (0,)), C.Gate("X", (1,), (0,), (1,), a=2)])
+    psi = run_gpu(circ, Q.QD_C128, stream)
+    want = np.zeros(18, np.complex128)
+    want[0] = want[15] = 0.7071067811865475
+    assert np.array_equal(psi, want)
+
+
+def test_config0_vs_bruteforce(stream):
+    c = C.config0()
+    psi = run_gpu(c, Q.QD_C128, stream)
+    assert max_abs(psi, O.run_circuit_operator(c)) <= 1e-12
+    assert max_abs(psi, O.run_circuit(c)) <= 1e-12
+    p = Q.qd_probabilities(_state_of(c, stream))
+    assert np.max(np.abs(p - O.probabilities(O.run_circuit(c)))) <= 1e-12
+
+
+def _state_of(c, stream, prec=Q.QD_C128):
+    """State handle after running c (caller frees via the module finalizer list)."""
+    s = Q.qd_state_init(c.dims, prec, stream)
+    _OPEN.append(s)
+    for g in c.gates:
+        Q.apply_circuit_gate(s, g, c.dims)
+    return s
+
+
+_OPEN = []
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _free_states():
+    yield
+    for s in _OPEN:
+        Q.qd_state_free(s)
+    _OPEN.clear()
+
+
+def test_config0_complex64(stream):
+    c = C.config0()
+    psi = run_gpu(c, Q.QD_C64, stream)
+    ref = O.run_circuit(c)
+    assert max_abs(psi, ref) <= c64_tol(len(c.gates), 3)
+    assert fidelity_loss(ref, psi) <= 1e-6
+
+
+def test_config1_shrink_500_gates(stream):
+    c = C.config1_shrink()
+    assert c.D == 10368 and len(c.gates) == 500
+    assert max_abs(run_gpu(c, Q.QD_C128, stream), O.run_circuit(c)) <= 1e-12
+
+
+@pytest.mark.parametrize("run_min", [1, 1024])
+def test_config1_shrink_forced_routes(stream, run_min):
+    """Same circuit with every gate forced to the direct kernel (run_min 1) or to the LDS tile
+    kernel wherever a tile fits (run_min 1024)."""
+    c = C.config1_shrink(200)
+    Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, run_min)
+    try:
+        psi = run_gpu(c, Q.QD_C128, stream)
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)
+    assert max_abs(psi, O.run_circuit(c)) <= 1e-12
+
+
+RANDOM_REGS = [(2, 3, 4, 3, 2), (3, 3, 3, 3, 3, 3, 3), (4, 2, 5, 2, 3, 2), (2,) * 12, (7, 5, 3, 2, 11),
+               (3, 2, 2, 4, 2, 3, 2, 2, 3), (5, 5, 5, 5)]
+
+
+@pytest.mark.parametrize("dims", RANDOM_REGS)
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_random_circuits(stream, dims, prec):
+    rng = C.seeded_rng(hash(dims) % 10000)
+    c = C.random_circuit(dims, 60, rng, max_targets=2, max_controls=2, max_dT=16)
+    c.init_amps = C.random_basis_superposition(O.register_size(dims), 9, rng)
+    psi = run_gpu(c, prec, stream)
+    ref = O.run_circuit(c)
+    if prec == Q.QD_C128:
+        assert max_abs(psi, ref) <= 1e-12
+    else:
+        assert max_abs(psi, ref) <= c64_tol(60, 16)
+        assert fidelity_loss(ref, psi) <= 1e-6
+
+
+def test_every_route_is_exercised(stream):
+    """One gate per kernel family and precision, each checked against the oracle."""
+    dims = (3, 2, 4, 3, 2, 2, 3, 2, 2, 2)
+    rng = C.seeded_rng(5)
+    D = O.register_size(dims)
+    psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    cases = [
+        ([0], (), (), C.haar_unitary(3, rng), Q.QD_ROUTE_DIRECT),
+        ([9], (), (), C.haar_unitary(2, rng), Q.QD_ROUTE_TILED),
+        ([6, 9], (0,), (2,), C.haar_unitary(6, rng), Q.QD_ROUTE_TILED),
+        ([2, 0], (9,), (1,), C.haar_unitary(12, rng), Q.QD_ROUTE_GENERIC),
+        ([9], (3,), (1,), O.z_gate(2), Q.QD_ROUTE_DIAG),
+        ([2, 3], (), (), np.diag(np.exp(2j * np.pi * rng.random(12))), Q.QD_ROUTE_DIAG),
+        ([1], (0,), (2,), O.x_gate(2, 1), Q.QD_ROUTE_DIRECT),
+        ([2, 0], (), (), np.eye(12)[rng.permutation(12)] * np.exp(1j * rng.random(12)), Q.QD_ROUTE_DIRECT),
+        ([8, 9], (), (), np.eye(4)[rng.permutation(4)], Q.QD_ROUTE_TILED),
+        ([0, 1, 2], (9,), (0,), C.haar_unitary(24, rng), Q.QD_ROUTE_GENERIC),
+    ]
+    for prec in (Q.QD_C128, Q.QD_C64):
+        for t, c, v, U, route in cases:
+            if prec == Q.QD_C128:
+                assert Q.qd_gate_route(dims, prec, t, c, v, U) == route, (t, c, route)
+            s = Q.qd_state_init(dims, prec, stream)
+            try:
+                Q.qd_state_upload(s, psi0)
+                Q.qd_apply_gate(s, t, c, v, U)
+                out = Q.qd_state_download(s)
+            finally:
+                Q.qd_state_free(s)
+            ref = O.apply_gate(psi0, dims, t, c, v, U)
+            tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, U.shape[0])
+            assert max_abs(out, ref) <= tol, (t, c, route, prec)
+
+
+@pytest.mark.parametrize("dims,targets", [((4, 4, 4, 2), [0, 1]), ((2, 2, 2, 2, 2, 2, 2), [6, 0, 3, 2, 5]),
+                                          ((3, 3, 3, 2), [2, 1, 0]), ((256,), [0]), ((2, 128, 2), [1, 2]),
+                                          ((4, 4, 4, 4, 4), [0, 1, 2, 3, 4])])
+def test_large_gates_generic(stream, dims, targets):
+    rng = C.seeded_rng(77)
+    dT = int(np.prod([dims[t] for t in targets]))
+    c = C.Circuit(dims, [C.Gate("U", tuple(targets), U=C.haar_unitary(dT, rng))],
+                  init_amps=C.random_basis_superposition(O.register_size(dims), 5, rng))
+    assert max_abs(run_gpu(c, Q.QD_C128, stream), O.run_circuit(c)) <= 1e-12
+
+
+@pytest.mark.parametrize("dims", [(2,), (7,), (256,), (2, 2), (3, 5)])
+def test_tiny_registers(stream, dims):
+    rng = C.seeded_rng(9)
+    gates = [C.Gate("F", (0,)), C.Gate("Z", (0,)), C.Gate("X", (0,), a=1),
+             C.Gate("U", (0,), U=C.haar_unitary(dims[0], rng))]
+    if len(dims) == 2:
+        gates += [C.Gate("X", (1,), (0,), (1,), a=1), C.Gate("U", (0, 1), U=C.haar_unitary(dims[0] * dims[1], rng)),
+                  C.Gate("U", (1,), (0,), (0,), U=C.haar_unitary(dims[1], rng))]
+    c = C.Circuit(dims, gates)
+    assert max_abs(run_gpu(c, Q.QD_C128, stream), O.run_circuit(c)) <= 1e-12
+
+
+def test_all_qudits_targeted_or_controlled(stream):
+    dims = (3, 2, 3)
+    rng = C.seeded_rng(10)
+    gates = [C.Gate("U", (0, 1, 2), U=C.haar_unitary(18, rng)),      # no free qudit
+             C.Gate("U", (2,), (0, 1), (2, 1), U=C.haar_unitary(3, rng)),  # a single slice
+             C.Gate("X", (1,), (0, 2), (0, 0), a=1), C.Gate("Z", (0,), (1, 2), (1, 2))]
+    c = C.Circuit(dims, gates, init_amps=C.random_basis_superposition(18, 18, rng))
+    assert max_abs(run_gpu(c, Q.QD_C128, stream), O.run_circuit(c)) <= 1e-12
+    assert max_abs(run_gpu(c, Q.QD_C64, stream), O.run_circuit(c)) <= c64_tol(4, 18)
+
+
+@pytest.mark.parametrize("param,values", [(Q.QD_TUNE_TILE_ELEMS, [256, 1024, 4096]),
+                                          (Q.QD_TUNE_TILE_BLOCK, [64, 128]),
+                                          (Q.QD_TUNE_DIRECT_BLOCK, [64, 192]),
+                                          (Q.QD_TUNE_DIRECT_SPT, [1, 4]),
+                                          (Q.QD_TUNE_DIAG_BLOCK, [64])])
+def test_tuning_parameters_keep_results(stream, param, values):
+    dims = (3, 2, 2, 4, 2, 3, 2, 2, 3)
+    rng = C.seeded_rng(11)
+    c = C.random_circuit(dims, 40, rng, max_dT=12)
+    ref = O.run_circuit(c)
+    for v in values:
+        Q.qd_tune_set(param, v)
+        try:
+            assert max_abs(run_gpu(c, Q.QD_C128, stream), ref) <= 1e-12, (param, v)
+        finally:
+            Q.qd_tune_set(param, 0)
+
+
+def test_wrap_torch_tensor(stream):
+    import torch
+    c = C.config0()
+    t = torch.zeros(2 * c.D, dtype=torch.float64, device="cuda")
+    s = Q.qd_state_wrap(c.dims, Q.QD_C128, t.data_ptr(), t.numel() * 8, stream)
+    try:
+        Q.qd_state_set_basis(s, [0] * 6)
+        for g in c.gates:
+            Q.apply_circuit_gate(s, g, c.dims)
+        Q.qd_state_sync(s)
+        host = t.cpu().numpy().view(np.complex128)
+        assert max_abs(host, O.run_circuit(c)) <= 1e-12
+        assert Q.qd_state_device_ptr(s) == t.data_ptr()
+    finally:
+        Q.qd_state_free(s)
+    assert torch.count_nonzero(t).item() > 0      # the library did not free torch's memory
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_state_wrap(c.dims, Q.QD_C128, t.data_ptr(), 100, stream)
+    assert e.value.code == Q.QD_EDIM
+
+
+def test_set_basis_upload_download(stream):
+    dims = (2, 3, 4)
+    s = Q.qd_state_init(dims, Q.QD_C128, stream)
+    try:
+        Q.qd_state_set_basis(s, [1, 2, 3])
+        psi = Q.qd_state_download(s)
+        assert np.array_equal(psi, O.basis_state(dims, [1, 2, 3]))
+        v = np.arange(24) + 1j * np.arange(24)[::-1]
+        Q.qd_state_upload(s, v)
+        assert np.array_equal(Q.qd_state_download(s), v)
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_state_set_basis(s, [2, 0, 0])
+        assert e.value.code == Q.QD_EINVAL
+    finally:
+        Q.qd_state_free(s)
+
+
+def test_readout_probabilities_norm_compare(stream):
+    import torch
+    rng = C.seeded_rng(12)
+    dims = (3, 4, 2, 5, 3)
+    c = C.random_circuit(dims, 30, rng)
+    ref = O.run_circuit(c)
+    s = _state_of(c, stream)
+    p = Q.qd_probabilities(s)
+    assert np.max(np.abs(p - O.probabilities(ref))) <= 1e-13
+    dev = torch.empty(c.D, dtype=torch.float64, device="cuda")
+    Q.qd_probabilities(s, dev.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), p)
+    n1, n2 = Q.qd_norm2(s), Q.qd_norm2(s)
+    assert n1 == n2 and abs(n1 - O.norm2(ref)) <= 1e-13
+    s32 = _state_of(c, stream, Q.QD_C64)
+    ma, fl, dr = Q.qd_compare(s, s32)
+    psi32 = Q.qd_state_download(s32)
+    oma, ofl, odr = O.compare(Q.qd_state_download(s), psi32)
+    assert abs(ma - oma) <= 1e-15 and abs(fl - ofl) <= 1e-13 and abs(dr - odr) <= 1e-13
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_compare(s32, s)
+    assert e.value.code == Q.QD_EDIM
+
+
+def test_validation_leaves_state_unchanged(stream):
+    dims = (2, 3, 4)
+    rng = C.seeded_rng(13)
+    s = Q.qd_state_init(dims, Q.QD_C128, stream)
+    try:
+        v = C.random_basis_superposition(24, 24, rng)
+        Q.qd_state_upload(s, v)
+        bad = [([1], [1], [0], O.x_gate(3, 1), Q.QD_EINVAL), ([1], [0], [2], O.x_gate(3, 1), Q.QD_EINVAL),
+               ([1], [], [], np.ones((3, 3)), Q.QD_ENOTUNITARY), ([2], [], [], O.x_gate(3, 1), Q.QD_EDIM),
+               ([7], [], [], O.x_gate(3, 1), Q.QD_EINVAL)]
+        for t, c, cv, U, code in bad:
+            with pytest.raises(Q.QDError) as e:
+                Q.qd_apply_gate(s, t, c, cv, U)
+            assert e.value.code == code
+        assert np.array_equal(Q.qd_state_download(s), v)
+    finally:
+        Q.qd_state_free(s)
+
+
+# ------------------------------------------------------------------------------ full size
+def _digit_sim(dims, gates, digs):
+    digs = list(digs)
+    for g in gates:
+        if all(digs[c] == v for c, v in zip(g.controls, g.cvals)):
+            t = g.targets[0]
+            digs[t] = (digs[t] + g.a) % dims[t]
+    return digs
+
+
+def test_config1_full_size_samples_and_norm(stream):
+    """D = 107,495,424: sampled outputs of single gates (every route the workload takes) against
+    the oracle evaluated one amplitude at a time, and the norm after all 500 gates."""
+    c = C.config1()
+    s = Q.qd_state_init(c.dims, Q.QD_C128, stream)
+    try:
+        for g in c.gates[:25]:
+            Q.apply_circuit_gate(s, g, c.dims)
+        rng = C.seeded_rng(14)
+        n = len(c.dims)
+        mid = n // 2
+        probes = [C.Gate("U", (n - 1,), U=C.haar_unitary(c.dims[n - 1], rng)),
+                  C.Gate("U", (0,), U=C.haar_unitary(c.dims[0], rng)),
+                  C.Gate("U", (mid,), U=C.haar_unitary(c.dims[mid], rng)),
+                  C.Gate("X", (mid,), (n - 1,), (1,), a=1),
+                  C.Gate("X", (n - 1,), (0,), (0,), a=1)]
+        for g in probes:
+            before = Q.qd_state_download(s)
+            Q.apply_circuit_gate(s, g, c.dims)
+            after = Q.qd_state_download(s)
+            idx = rng.choice(c.D, 3000, replace=False)
+            want = O.apply_gate_at(before, c.dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, c.dims), idx)
+            assert max_abs(after[idx], want) <= 1e-12, g
+            del before, after
+        for g in c.gates[25:]:
+            Q.apply_circuit_gate(s, g, c.dims)
+        assert abs(Q.qd_norm2(s) - 1.0) <= 1e-12
+    finally:
+        Q.qd_state_free(s)
+
+
+def test_config1_full_size_permutation_circuit(stream):
+    """Permutation-only circuit on the full hybrid register: the basis state lands exactly on the
+    index an integer digit simulation predicts."""
+    c = C.config1()
+    rng = C.seeded_rng(15)
+    pc = C.permutation_circuit(c.dims, 300, rng)
+    start = [int(rng.integers(d)) for d in c.dims]
+    s = Q.qd_state_init(c.dims, Q.QD_C128, stream)
+    try:
+        Q.qd_state_set_basis(s, start)
+        for g in pc.gates:
+            Q.apply_circuit_gate(s, g, c.dims)
+        psi = Q.qd_state_download(s)
+    finally:
+        Q.qd_state_free(s)
+    end = O.index_of(_digit_sim(c.dims, pc.gates, start), c.dims)
+    nz = np.flatnonzero(psi)
+    assert list(nz) == [end] and psi[end] == 1.0
+
+
+def test_config1_full_size_diagonal_closed_form(stream):
+    c = C.config1()
+    rng = C.seeded_rng(16)
+    dc = C.diagonal_circuit(c.dims, 60, rng)
+    psi0 = C.random_basis_superposition(c.D, 4096, rng)
+    s = Q.qd_state_init(c.dims, Q.QD_C128, stream)
+    try:
+        Q.qd_state_upload(s, psi0)
+        for g in dc.gates:
+            Q.apply_circuit_gate(s, g, c.dims)
+        psi = Q.qd_state_download(s)
+    finally:
+        Q.qd_state_free(s)
+    idx = np.flatnonzero(psi0)
+    st = O.strides(c.dims)
+    want = []
+    for x in idx:
+        dg = [(int(x) // st[i]) % c.dims[i] for i in range(len(c.dims))]
+        ang = sum(dg[g.targets[0]] / c.dims[g.targets[0]] for g in dc.gates
+                  if all(dg[cc] == v for cc, v in zip(g.controls, g.cvals)))
+        want.append(psi0[x] * complex(math.cos(2 * math.pi * ang), math.sin(2 * math.pi * ang)))
+    assert max_abs(psi[idx], np.array(want)) <= 1e-12
+    assert np.count_nonzero(psi) == len(idx)

@@ -1,0 +1,238 @@
+"""Host-side checks of libqd (CPU only: no call here touches a GPU).
+
+* the library loads and exports every function include/qd.h declares;
+* register strides, named gate matrices and gate classes agree with the oracle / definitions;
+* every validation error code of qd_apply_gate is produced by qd_validate_gate;
+* the fusion planner returns valid in-order partitions within the block bound;
+* the magic-number division used by the kernels is exact (compiled with g++ on the host).
+"""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+import paper_2211_07918_amd as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qd.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(qd_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = Q.load()
+    names = _declared_functions()
+    assert len(names) >= 40
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps each of them under the same name
+    assert not [n for n in names if not hasattr(Q, n)]
+
+
+def test_nm_shows_c_linkage():
+    out = subprocess.run(["nm", "-D", "--defined-only", Q.lib_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (qd_[a-z0-9_]+)$", out, flags=re.M))
+    assert set(_declared_functions()) <= exported
+
+
+@pytest.mark.parametrize("dims", [(2,), (3, 2, 4), (2, 3, 3), (4,) * 14, (3,) * 20, (256, 2, 255)])
+def test_register_strides(dims):
+    D, st = Q.qd_register_strides(dims)
+    assert D == O.register_size(dims)
+    assert st == O.strides(dims)
+
+
+def test_register_errors():
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_register_strides([2, 1])
+    assert e.value.code == Q.QD_EDIM
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_register_strides([257])
+    assert e.value.code == Q.QD_EDIM
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_register_strides([2] * 65)
+    assert e.value.code == Q.QD_EINVAL
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_register_strides([256] * 8)          # 2^64 overflows int64
+    assert e.value.code == Q.QD_EOVERFLOW
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8, 9, 16, 255, 256])
+def test_named_gates_match_oracle(d):
+    assert np.array_equal(Q.qd_gate_matrix(Q.QD_GATE_Z, d), O.z_gate(d))
+    assert np.array_equal(Q.qd_gate_matrix(Q.QD_GATE_F, d), O.f_gate(d))
+    assert np.array_equal(Q.qd_gate_matrix(Q.QD_GATE_I, d), np.eye(d))
+    for a in sorted({1, d // 2, d - 1}):
+        assert np.array_equal(Q.qd_gate_matrix(Q.QD_GATE_X, d, a), O.x_gate(d, a))
+
+
+def test_named_gate_errors():
+    for a in (0, 3, -1):
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_gate_matrix(Q.QD_GATE_X, 3, a)
+        assert e.value.code == Q.QD_EINVAL
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_gate_matrix(7, 3)
+    assert e.value.code == Q.QD_EINVAL
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_gate_matrix(Q.QD_GATE_F, 1)
+    assert e.value.code == Q.QD_EDIM
+
+
+def test_validation_codes():
+    dims = [2, 3, 4]
+    X3 = O.x_gate(3, 1)
+    ok = Q.qd_validate_gate
+    assert ok(dims, [1], [0], [1], X3) == Q.QD_OK
+    assert ok(dims, [1], [1], [0], X3) == Q.QD_EINVAL            # control == target
+    assert ok(dims, [1, 1], [], [], np.eye(9)) == Q.QD_EINVAL    # duplicate target
+    assert ok(dims, [3], [], [], X3) == Q.QD_EINVAL              # target out of range
+    assert ok(dims, [1], [0], [2], X3) == Q.QD_EINVAL            # control value >= d_c
+    assert ok(dims, [1], [0], [-1], X3) == Q.QD_EINVAL
+    assert ok(dims, [1], [5], [0], X3) == Q.QD_EINVAL            # control out of range
+    assert ok(dims, [1], [0, 0], [0, 1], X3) == Q.QD_EINVAL      # duplicate control
+    assert ok(dims, [], [], [], X3) == Q.QD_EINVAL               # no target
+    assert ok([2, 2, 2], [0, 1, 2], [0], [0], np.eye(8)) == Q.QD_EINVAL  # k + m > n
+    bad = np.ones((3, 3)) / 3.0
+    assert ok(dims, [1], [], [], bad) == Q.QD_ENOTUNITARY
+    assert ok(dims, [1], [], [], bad, Q.QD_FLAG_SKIP_UNITARY_CHECK) == Q.QD_OK
+    nan = X3.copy()
+    nan[0, 0] = np.nan
+    assert ok(dims, [1], [], [], nan, Q.QD_FLAG_SKIP_UNITARY_CHECK) == Q.QD_ENOTUNITARY
+    assert ok([4] * 6, [0, 1, 2, 3, 4, 5], [], [], np.eye(4096)) == Q.QD_EDIM  # d_T > 1024
+    assert ok(dims, [2], [], [], X3) == Q.QD_EDIM                # U size != d_T (binding check)
+    assert ok(dims, [1], [], [], X3 * (1 + 1e-9)) == Q.QD_ENOTUNITARY
+    assert ok(dims, [1], [], [], X3 * (1 + 1e-12)) == Q.QD_OK
+
+
+def test_gate_classes():
+    assert Q.qd_gate_class(O.z_gate(5)) == Q.QD_CLASS_DIAGONAL
+    assert Q.qd_gate_class(O.x_gate(5, 2)) == Q.QD_CLASS_MONOMIAL
+    assert Q.qd_gate_class(O.f_gate(3)) == Q.QD_CLASS_DENSE
+    sw = C.qudit_qft_gates(4, 2)[-1].U
+    assert Q.qd_gate_class(sw) == Q.QD_CLASS_MONOMIAL
+    assert Q.qd_gate_class(np.diag(np.exp(1j * np.arange(16)))) == Q.QD_CLASS_DIAGONAL
+    assert Q.qd_gate_class(np.eye(1)) == Q.QD_CLASS_DIAGONAL
+
+
+def test_routes():
+    dims = [2, 3, 4, 3, 2, 2, 3, 2, 2, 2]   # strides of the last qudits are 1, 2, 4, 8, ...
+    r = lambda t, U, c=(), v=(), prec=Q.QD_C128: Q.qd_gate_route(dims, prec, t, c, v, U)
+    assert r([0], O.f_gate(2)) == Q.QD_ROUTE_DIRECT
+    assert r([9], O.f_gate(2)) == Q.QD_ROUTE_TILED
+    assert r([6], O.f_gate(3)) == Q.QD_ROUTE_TILED
+    assert r([9], O.z_gate(2)) == Q.QD_ROUTE_DIAG
+    assert r([1], O.x_gate(3, 1), [0], [1]) == Q.QD_ROUTE_DIRECT
+    assert r([1, 2], np.eye(12)[::-1]) == Q.QD_ROUTE_DIRECT        # monomial d_T = 12
+    assert r([1, 2], C.haar_unitary(12, C.seeded_rng(1))) == Q.QD_ROUTE_GENERIC
+    assert r([1, 2, 3], C.haar_unitary(36, C.seeded_rng(1))) == Q.QD_ROUTE_GENERIC
+    Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 1)
+    try:
+        assert r([9], O.f_gate(2)) == Q.QD_ROUTE_DIRECT
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)
+    assert Q.qd_tune_get(Q.QD_TUNE_RUN_MIN) == 16
+
+
+def test_tune_parameters():
+    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 128), (Q.QD_TUNE_DIRECT_SPT, 1), (Q.QD_TUNE_TILE_ELEMS, 1024)):
+        old = Q.qd_tune_get(p)
+        Q.qd_tune_set(p, v)
+        assert Q.qd_tune_get(p) == v
+        Q.qd_tune_set(p, 0)
+        assert Q.qd_tune_get(p) == old
+    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 100), (Q.QD_TUNE_DIRECT_SPT, 3), (Q.QD_TUNE_TILE_ELEMS, 1000), (42, 1)):
+        with pytest.raises(Q.QDError):
+            Q.qd_tune_set(p, v)
+
+
+# ------------------------------------------------------------------------------ fusion planner
+def _check_plan(dims, gates, blocks, nb, maxb):
+    assert len(blocks) == len(gates)
+    assert blocks == sorted(blocks) and (not blocks or (blocks[0] == 0 and blocks[-1] == nb - 1))
+    for b in range(nb):
+        members = [g for g, bb in zip(gates, blocks) if bb == b]
+        assert members
+        win = set(q for g in members for q in g.qudits())
+        assert int(np.prod([dims[q] for q in win])) <= maxb
+    # greedy: the first gate of every block would not fit in the previous block's window
+    for i in range(1, len(gates)):
+        if blocks[i] != blocks[i - 1]:
+            prev = set(q for g, bb in zip(gates, blocks) if bb == blocks[i - 1] for q in g.qudits())
+            assert int(np.prod([dims[q] for q in prev | set(gates[i].qudits())])) > maxb
+
+
+@pytest.mark.parametrize("maxb", [16, 64, 81, 128])
+def test_fuse_plan_valid(maxb):
+    for circ in (C.config2(6), C.config3(8, 6), C.config1_shrink(60), C.config0()):
+        gates = [g for g in circ.gates if np.prod([circ.dims[q] for q in g.qudits()]) <= maxb]
+        blocks, nb = Q.qd_fuse_plan(circ.dims, gates, maxb)
+        _check_plan(circ.dims, gates, blocks, nb, maxb)
+
+
+def test_fuse_plan_counts():
+    c2 = C.config2(14)
+    _, nb = Q.qd_fuse_plan(c2.dims, c2.gates, 64)
+    assert 40 <= nb <= 70
+    c3 = C.config3(20, 30)
+    _, nb = Q.qd_fuse_plan(c3.dims, c3.gates, 81)
+    assert nb <= 285
+
+
+def test_fuse_plan_errors():
+    c = C.config3(4, 2)
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_fuse_plan(c.dims, c.gates, 8)       # a 9x9 gate does not fit
+    assert e.value.code == Q.QD_EDIM
+    with pytest.raises(Q.QDError) as e:
+        Q.qd_fuse_plan(c.dims, c.gates, 129)
+    assert e.value.code == Q.QD_EINVAL
+
+
+# ------------------------------------------------------------------------------ magic division
+def test_magic_division_exact(tmp_path):
+    src = tmp_path / "magic_check.cpp"
+    src.write_text(r'''
+#include <cstdio>
+#include <cstdint>
+#include <random>
+#include "qd_magic.h"
+int main() {
+  std::mt19937_64 rng(7);
+  const uint32_t edge[] = {0u, 1u, 2u, 3u, 255u, 256u, 65535u, 65536u, 2147483647u, 2147483648u,
+                           4294967294u, 4294967295u, 3486784400u, 107495423u};
+  uint64_t bad = 0, n_checks = 0;
+  auto check = [&](uint32_t d, uint32_t n) {
+    const qd::Magic32 m = qd::make_magic32(d);
+    ++n_checks;
+    if (qd::magic_div(n, m) != n / d) ++bad;
+  };
+  for (uint32_t d = 1; d <= 4096; ++d) {
+    for (uint32_t n : edge) check(d, n);
+    for (int i = 0; i < 2000; ++i) check(d, uint32_t(rng()));
+    for (uint32_t q = 1; q < 64; ++q) {           // around multiples of d
+      const uint64_t base = uint64_t(q) * d * 977u;
+      if (base + 1 < 4294967296ull && base >= 1) { check(d, uint32_t(base)); check(d, uint32_t(base - 1)); check(d, uint32_t(base + 1)); }
+    }
+  }
+  const uint32_t bigd[] = {6561u, 59049u, 531441u, 1u << 20, 3486784401u, 4294967295u, 107495424u};
+  for (uint32_t d : bigd) { for (uint32_t n : edge) check(d, n); for (int i = 0; i < 100000; ++i) check(d, uint32_t(rng())); }
+  std::printf("%llu %llu\n", (unsigned long long)bad, (unsigned long long)n_checks);
+  return bad != 0;
+}
+''')
+    exe = tmp_path / "magic_check"
+    inc = os.path.join(ROOT, "paper_2211_07918_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", inc, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    bad, total = map(int, r.stdout.split())
+    assert r.returncode == 0 and bad == 0 and total > 8_000_000
