@@ -182,27 +182,32 @@ int qd_apply_gate_ex(qd_state* s, const int32_t* targets, int32_t k, const int32
 
 /* ---------------------------------------------------------------- gate fusion (Sec. 3.6) */
 
-/* Fusion plan, host only: groups consecutive gates greedily, in circuit order, while the union
- * W of their targets and controls keeps prod_{w in W} dims[w] <= max_block_dim. This is the
- * paper's "multiply the Moment operators together" (Sec. 3.6) bounded to blocks of at most
- * max_block_dim (2 <= max_block_dim <= 128). block_of_gate[g] receives the block index of gate
- * g (caller-allocated, g entries); *nblocks the number of blocks. A gate whose own qudits exceed
- * max_block_dim is QD_EDIM. */
+/* Fusion plan, host only: the paper multiplies the Moment operators of a whole circuit into one
+ * operator (Sec. 3.6); here the products are bounded to blocks whose window W (the union of the
+ * members' targets and controls) keeps prod_{w in W} dims[w] <= max_block_dim
+ * (2 <= max_block_dim <= 128). A block starts at the first gate not yet placed; a later gate joins
+ * it if the window stays within the bound and the gate touches no qudit of a gate skipped so far
+ * (so it commutes with every gate it moves ahead of); members keep their circuit order.
+ * block_of_gate[g] receives the block index of gate g (caller-allocated, g entries; blocks run in
+ * index order); *nblocks the number of blocks. A gate whose own qudits exceed max_block_dim is
+ * QD_EDIM. */
 int qd_fuse_plan(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g,
                  int32_t max_block_dim, int32_t* block_of_gate, int32_t* nblocks);
 
-/* Plan (as qd_fuse_plan) and build every block on the GPU in FP64: block = E_last ... E_first,
- * E_i the gate embedded in the block's window (window qudits in ascending order, the first most
- * significant). Also emits the FP32 and split-BF16 (hi, lo) copies used by qd_apply_fused.
+/* Plan (as qd_fuse_plan) and build every block on the GPU in FP64: block = E_last ... E_first
+ * over the block's members, E_i the gate embedded in the block's window (window qudits in
+ * ascending order, the first most significant). Also emits the FP32 and split-BF16 (hi, lo) copies used by qd_apply_fused.
  * Gates are validated as in qd_apply_gate. Asynchronous on hip_stream. */
 int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int32_t max_block_dim,
             void* hip_stream, qd_fused** out);
 
-/* Number of blocks, and per block: window size k, window qudits (caller array of >= 16 ints),
- * block dimension B, first gate index and gate count. */
+/* Number of blocks, and per block: window size k, window qudits (caller array of >= 64 ints,
+ * ascending), block dimension B, first member gate and member count; qd_fused_block_gates writes
+ * the member gate indices (ngates ints, ascending). */
 int qd_fused_count(const qd_fused* f, int32_t* nblocks);
 int qd_fused_block_info(const qd_fused* f, int32_t b, int32_t* k, int32_t* window, int32_t* B,
                         int32_t* first_gate, int32_t* ngates);
+int qd_fused_block_gates(const qd_fused* f, int32_t b, int32_t* gates_out);
 
 /* Copy block b (B x B complex FP64, row-major, interleaved) to host memory; synchronises. */
 int qd_fused_download_block(const qd_fused* f, int32_t b, double* out);
@@ -234,6 +239,18 @@ int qd_norm2(const qd_state* s, double* out);
  * QD_EDIM if the registers differ or ref is not complex128. Synchronises. */
 int qd_compare(const qd_state* ref64, const qd_state* s, double* max_abs, double* fid_loss,
                double* norm_drift);
+
+/* qd_compare plus the normalised variant, written to out[0..4]:
+ *   out[0] max_x |psi_x - ref_x|, out[1] 1 - |<ref|psi>|^2, out[2] | ||psi||^2 - 1 |,
+ *   out[3] ||psi||^2, out[4] 1 - |<ref|psi>|^2 / ||psi||^2 (direction error only).
+ * Same requirements and errors as qd_compare. Synchronises. */
+int qd_compare_ex(const qd_state* ref64, const qd_state* s, double* out5);
+
+/* Restore the normalisation of Eq. (1) (sum |alpha|^2 = 1): ||psi||^2 by the FP64 reduction of
+ * qd_norm2, then every amplitude scaled by 1/sqrt(||psi||^2) in the state's precision.
+ * *norm2_before (may be NULL) receives the squared norm before scaling. QD_EINVAL if the norm is
+ * zero or not finite (the state is left untouched). Synchronises. */
+int qd_normalize(qd_state* s, double* norm2_before);
 
 /* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
 

@@ -29,8 +29,9 @@ __all__ = [
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
-    "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_download_block",
-    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare",
+    "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_block_gates", "qd_fused_download_block",
+    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare", "qd_compare_ex",
+    "qd_normalize",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
     "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
     "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_stream_copy",
@@ -98,11 +99,14 @@ _SIGS = {
     "qd_fused_count": (C.c_int, [_P, _I32P]),
     "qd_fused_block_info": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I32P, _I32P, _I32P]),
     "qd_fused_download_block": (C.c_int, [_P, C.c_int32, _DP]),
+    "qd_fused_block_gates": (C.c_int, [_P, C.c_int32, _I32P]),
     "qd_apply_fused": (C.c_int, [_P, _P, C.c_int32]),
     "qd_fused_free": (None, [_P]),
     "qd_probabilities": (C.c_int, [_P, _DP, C.c_int32]),
     "qd_norm2": (C.c_int, [_P, _DP]),
     "qd_compare": (C.c_int, [_P, _P, _DP, _DP, _DP]),
+    "qd_compare_ex": (C.c_int, [_P, _P, _DP]),
+    "qd_normalize": (C.c_int, [_P, _DP]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
     "qd_batch_offset": (C.c_int, [_P, C.c_int32, _I64P]),
@@ -359,8 +363,14 @@ def qd_fused_block_info(f: int, b: int):
     k, B, first, ng = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
     win = (C.c_int32 * 64)()
     _check(load().qd_fused_block_info(_P(f), b, C.byref(k), win, C.byref(B), C.byref(first), C.byref(ng)))
+    gs = (C.c_int32 * max(1, ng.value))()
+    _check(load().qd_fused_block_gates(_P(f), b, gs))
     return {"window": [int(x) for x in win[:k.value]], "B": int(B.value), "first_gate": int(first.value),
-            "ngates": int(ng.value)}
+            "ngates": int(ng.value), "gates": [int(x) for x in gs[:ng.value]]}
+
+
+def qd_fused_block_gates(f: int, b: int):
+    return qd_fused_block_info(f, b)["gates"]
 
 
 def qd_fused_download_block(f: int, b: int) -> np.ndarray:
@@ -401,6 +411,19 @@ def qd_compare(ref64: int, s: int):
     a, b, c = C.c_double(), C.c_double(), C.c_double()
     _check(load().qd_compare(_P(ref64), _P(s), C.byref(a), C.byref(b), C.byref(c)))
     return float(a.value), float(b.value), float(c.value)
+
+
+def qd_compare_ex(ref64: int, s: int) -> dict:
+    out = (C.c_double * 5)()
+    _check(load().qd_compare_ex(_P(ref64), _P(s), out))
+    return {"max_abs": out[0], "fid_loss": out[1], "norm_drift": out[2], "norm2": out[3],
+            "fid_loss_normalized": out[4]}
+
+
+def qd_normalize(s: int) -> float:
+    v = C.c_double()
+    _check(load().qd_normalize(_P(s), C.byref(v)))
+    return float(v.value)
 
 
 # ------------------------------------------------------------------------------ batch

@@ -14,58 +14,73 @@
 namespace qd {
 
 // ------------------------------------------------------------------------------------------ planner
+// A block starts at the first gate not yet placed. Later gates join it while the window (union of
+// the members' targets and controls) spans at most max_block basis states. A gate that does not
+// join is skipped, and its qudits become blocked: a later gate may still join only if it commutes
+// with every skipped gate it would move ahead of. Two gates commute exactly when their qudits are
+// disjoint, or when both are diagonal (controlled phases, Z_d). Members keep their circuit order,
+// so each block is an exact product of Moment operators up to such commutations.
 int plan_fusion(const Register& r, const qd_gate* gates, int32_t g, int32_t max_block,
                 std::vector<int32_t>* block_of, std::vector<FusedBlockInfo>* blocks) {
   if (g < 0 || (g > 0 && !gates)) return fail(QD_EINVAL, "bad gate list");
   if (max_block < 2 || max_block > QD_MAX_FUSED_DIM) return fail(QD_EINVAL, "max_block_dim must be 2..128");
-  block_of->assign(size_t(g), 0);
+  block_of->assign(size_t(g), -1);
   blocks->clear();
-  bool in_win[QD_MAX_QUDITS] = {};
-  int64_t wdim = 1;
+  std::vector<uint64_t> mask(size_t(g), 0);    // qudit set of each gate (n <= 64)
+  std::vector<char> diag(size_t(g), 0);
   for (int i = 0; i < g; ++i) {
     const qd_gate& G = gates[i];
     if (G.k < 1 || !G.targets || G.m < 0 || (G.m > 0 && (!G.controls || !G.control_values)))
       return fail(QD_EINVAL, "malformed gate " + std::to_string(i));
-    bool mine[QD_MAX_QUDITS] = {};
     int64_t own = 1;
     for (int j = 0; j < G.k + G.m; ++j) {
       const int q = j < G.k ? G.targets[j] : G.controls[j - G.k];
       if (q < 0 || q >= r.n) return fail(QD_EINVAL, "qudit out of range in gate " + std::to_string(i));
-      if (!mine[q]) own *= r.dims[q];
-      mine[q] = true;
+      if (!(mask[i] >> q & 1)) own *= r.dims[q];
+      mask[i] |= uint64_t(1) << q;
     }
     if (own > max_block) return fail(QD_EDIM, "gate " + std::to_string(i) + " spans more than max_block_dim");
-    int64_t uni = wdim;
-    for (int q = 0; q < r.n; ++q)
-      if (mine[q] && !in_win[q]) uni *= r.dims[q];
-    if (blocks->empty() || uni > max_block) {
-      if (!blocks->empty()) {
-        FusedBlockInfo& prev = blocks->back();
-        prev.k = 0;
-        for (int q = 0; q < r.n; ++q)
-          if (in_win[q]) prev.window[prev.k++] = q;
-        prev.B = int32_t(wdim);
-      }
-      FusedBlockInfo nb{};
-      nb.first_gate = i;
-      nb.ngates = 0;
-      blocks->push_back(nb);
-      std::memset(in_win, 0, sizeof(in_win));
-      wdim = 1;
-      uni = own;
-    }
-    for (int q = 0; q < r.n; ++q)
-      if (mine[q]) in_win[q] = true;
-    wdim = uni;
-    blocks->back().ngates += 1;
-    (*block_of)[i] = int32_t(blocks->size() - 1);
+    int64_t dT = 1;
+    for (int j = 0; j < G.k; ++j) dT *= r.dims[G.targets[j]];
+    diag[i] = G.U && classify(G.U, int(dT)) == QD_CLASS_DIAGONAL;
   }
-  if (!blocks->empty()) {
-    FusedBlockInfo& last = blocks->back();
-    last.k = 0;
+  auto span = [&](uint64_t m) {
+    int64_t p = 1;
     for (int q = 0; q < r.n; ++q)
-      if (in_win[q]) last.window[last.k++] = q;
-    last.B = int32_t(wdim);
+      if (m >> q & 1) p *= r.dims[q];
+    return p;
+  };
+  const uint64_t all = r.n == 64 ? ~uint64_t(0) : ((uint64_t(1) << r.n) - 1);
+  int first = 0;
+  while (first < g) {
+    FusedBlockInfo nb{};
+    const int bidx = int(blocks->size());
+    // qudits of skipped non-diagonal gates (block everything) and of skipped diagonal gates
+    // (block only non-diagonal gates)
+    uint64_t win = mask[first], blocked = 0, blocked_diag = 0;
+    nb.members.push_back(first);
+    (*block_of)[first] = bidx;
+    for (int i = first + 1; i < g; ++i) {
+      if ((*block_of)[i] >= 0) continue;
+      const bool passes = !(mask[i] & blocked) && (diag[i] || !(mask[i] & blocked_diag));
+      if (passes && span(win | mask[i]) <= max_block) {
+        win |= mask[i];
+        nb.members.push_back(i);
+        (*block_of)[i] = bidx;
+        continue;
+      }
+      if (diag[i]) blocked_diag |= mask[i];
+      else blocked |= mask[i];
+      if ((blocked | win) == all && (blocked & win) == win) break;  // nothing can join any more
+    }
+    nb.k = 0;
+    for (int q = 0; q < r.n; ++q)
+      if (win >> q & 1) nb.window[nb.k++] = q;
+    nb.B = int32_t(span(win));
+    nb.first_gate = nb.members.front();
+    nb.ngates = int32_t(nb.members.size());
+    blocks->push_back(nb);
+    while (first < g && (*block_of)[first] >= 0) ++first;
   }
   return QD_OK;
 }
@@ -102,7 +117,7 @@ int embed_block(qd_fused* f, int b) {
   return QD_OK;
 }
 
-static int pad_k(int B) { return ((2 * B + 15) / 16) * 16; }
+static int pad_k(int B) { return fused_kpad(B); }
 
 }  // namespace qd
 
@@ -184,7 +199,7 @@ int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int
     e = hipMemcpyAsync(d.u64, eye.data(), eye.size() * sizeof(double), hipMemcpyHostToDevice, f->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "fused block init"));
-    for (int i = d.info.first_gate; i < d.info.first_gate + d.info.ngates; ++i) {
+    for (int i : d.info.members) {
       const qd_gate& G = gates[i];
       int32_t t[QD_MAX_QUDITS], c[QD_MAX_QUDITS];
       for (int j = 0; j < G.k; ++j) t[j] = pos[G.targets[j]];
@@ -202,6 +217,10 @@ int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int
     if (e != hipSuccess) return cleanup(hip_fail(e, "fused block build"));
     rc = embed_block(f, int(b));
     if (rc) return cleanup(rc);
+    if (r.D <= int64_t(0xFFFFFFFFll)) {
+      rc = fused_geometry(r, &d);
+      if (rc) return cleanup(rc);
+    }
     d.host64.resize(2 * size_t(B) * B);
   }
   // host copies of the FP64 blocks for the FP64 apply path
@@ -233,6 +252,14 @@ int qd_fused_block_info(const qd_fused* f, int32_t b, int32_t* k, int32_t* windo
   if (B) *B = i.B;
   if (first) *first = i.first_gate;
   if (ng) *ng = i.ngates;
+  return QD_OK;
+}
+
+int qd_fused_block_gates(const qd_fused* f, int32_t b, int32_t* gates_out) {
+  if (!f || !gates_out) return fail(QD_EINVAL, "null argument");
+  if (b < 0 || b >= int32_t(f->dev.size())) return fail(QD_EINVAL, "block index out of range");
+  const FusedBlockInfo& i = f->dev[b].info;
+  for (size_t j = 0; j < i.members.size(); ++j) gates_out[j] = i.members[j];
   return QD_OK;
 }
 
@@ -277,6 +304,9 @@ void qd_fused_free(qd_fused* f) {
     if (d.a32) (void)hipFree(d.a32);
     if (d.ahi) (void)hipFree(d.ahi);
     if (d.alo) (void)hipFree(d.alo);
+    if (d.tab_hoff) (void)hipFree(d.tab_hoff);
+    if (d.tab_yh) (void)hipFree(d.tab_yh);
+    if (d.tab_lmap) (void)hipFree(d.tab_lmap);
   }
   delete f;
 }

@@ -14,13 +14,36 @@ struct FusedBlockInfo {
   int32_t k;                        // window size
   int32_t window[QD_MAX_QUDITS];    // window qudits, ascending (first = most significant)
   int32_t B;                        // block dimension = prod of the window's dims
-  int32_t first_gate;
-  int32_t ngates;
+  int32_t first_gate;              // first member (in circuit order)
+  int32_t ngates;                  // number of members
+  std::vector<int32_t> members;    // gate indices, ascending
+};
+
+// Kernel arguments of the matrix-core block application (by value).
+struct FusedArgs {
+  float2* psi;
+  const float* a32;                 // Kp x Kp real embedding, FP32
+  const __bf16* ahi;                // BF16 split
+  const __bf16* alo;
+  int32_t Kp;                       // leading dimension of the A arrays (64, 128, 192 or 256)
+  int32_t twoB;                     // 2B real rows in use
+  uint32_t BL, dH, E, NT;           // run length, runs, amplitudes and columns per tile
+  Magic32 blm;                      // division by BL
+  SliceMap tiles;                   // tile index -> global offset of its first run
+  const int64_t* hoff;              // dH run offsets from the tile origin
+  const int32_t* yh;                // window-local index contributed by each run
+  const uint32_t* lmap;             // BL entries: (column << 16) | window-local index part
 };
 
 struct FusedBlockDev {
   FusedBlockInfo info{};
-  int Kp = 0;                       // padded real dimension (2B rounded up to 16)
+  int Kp = 0;                       // padded real dimension (2B rounded up to 32)
+  int variant = 0;                  // kernel shape: rows of A per wave and columns per tile
+  bool geom_ok = false;
+  FusedArgs args{};
+  int64_t* tab_hoff = nullptr;
+  int32_t* tab_yh = nullptr;
+  uint32_t* tab_lmap = nullptr;
   double* u64 = nullptr;            // B x B complex FP64, row-major interleaved
   float* a32 = nullptr;             // Kp x Kp real embedding, FP32
   __hip_bfloat16* ahi = nullptr;    // BF16 split of a32: hi
@@ -31,6 +54,8 @@ struct FusedBlockDev {
 int plan_fusion(const Register& r, const qd_gate* gates, int32_t g, int32_t max_block,
                 std::vector<int32_t>* block_of, std::vector<FusedBlockInfo>* blocks);
 int launch_fused_block(qd_state* s, const struct ::qd_fused* f, int b, int mode);
+int fused_geometry(const Register& r, FusedBlockDev* d);
+int fused_kpad(int B);            // leading dimension of the real embedding for block dimension B
 
 }  // namespace qd
 

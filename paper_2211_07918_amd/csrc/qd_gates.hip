@@ -159,27 +159,55 @@ struct TileArgs {
   SliceMap inner;                 // slice index inside a tile -> LDS index of its y = 0 amplitude
   uint32_t BL;                    // run length (amplitudes of the low suffix)
   uint32_t dH;                    // number of runs (product of the high targets' dims)
+  Magic32 blm;                    // division by BL
   int64_t hoff[kMaxTileRuns];     // global offset of run h from the tile origin
   int64_t toff[DT];               // LDS offset of target combination y
   int64_t doff[DT];               // monomial: LDS offset of the row column y moves to
   OP op;
 };
 
+// Amplitudes a thread moves per tile: the tile holds at most 256 * kTileEpt<R> amplitudes.
+template <typename R> struct TileEpt;
+template <> struct TileEpt<double> { static constexpr int value = 8; };
+template <> struct TileEpt<float> { static constexpr int value = 16; };
+
 template <typename R, int DT, typename OP>
 __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
   using C = typename CxT<R>::T;
+  constexpr int EPT = TileEpt<R>::value;
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int64_t s_hoff[kMaxTileRuns];
   C* lds = reinterpret_cast<C*>(lds_raw);
   C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
   const uint32_t bs = blockDim.x, tid = threadIdx.x;
+  const uint32_t E = a.BL * a.dH;
+#pragma unroll
+  for (int h = 0; h < kMaxTileRuns; ++h)
+    if (int(tid) == h) s_hoff[h] = a.hoff[h];
+  __syncthreads();
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = sm_offset(a.tiles, tile);
+    // every load of the tile is issued before the first LDS write
+    // (real and imaginary parts in separate scalar arrays so they stay in registers)
+    R vr[EPT], vi[EPT];
 #pragma unroll
-    for (int h = 0; h < kMaxTileRuns; ++h) {
-      if (h < int(a.dH)) {
-        const C* src = psi + g0 + a.hoff[h];
-        C* dst = lds + h * a.BL;
-        for (uint32_t l = tid; l < a.BL; l += bs) dst[l] = src[l];
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t idx = tid + e * bs;
+      if (idx < E) {
+        const uint32_t h = magic_div(idx, a.blm);
+        const C t = psi[g0 + s_hoff[h] + (idx - h * a.BL)];
+        vr[e] = t.x;
+        vi[e] = t.y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t idx = tid + e * bs;
+      if (idx < E) {
+        C t;
+        t.x = vr[e];
+        t.y = vi[e];
+        lds[idx] = t;
       }
     }
     __syncthreads();
@@ -192,14 +220,26 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < kMaxTileRuns; ++h) {
-      if (h < int(a.dH)) {
-        C* dst = psi + g0 + a.hoff[h];
-        const C* src = lds + h * a.BL;
-        for (uint32_t l = tid; l < a.BL; l += bs) dst[l] = src[l];
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t idx = tid + e * bs;
+      if (idx < E) {
+        const C t = lds[idx];
+        vr[e] = t.x;
+        vi[e] = t.y;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t idx = tid + e * bs;
+      if (idx < E) {
+        const uint32_t h = magic_div(idx, a.blm);
+        C t;
+        t.x = vr[e];
+        t.y = vi[e];
+        psi[g0 + s_hoff[h] + (idx - h * a.BL)] = t;
+      }
+    }
+    if (tile + gridDim.x < a.tiles.count) __syncthreads();
   }
 }
 
@@ -342,8 +382,8 @@ static void fill_mono(const GatePlan& p, MonoOp<R, DT>* op) {
 }
 
 // LDS tile geometry: the low suffix L = {pq, ..., n-1} of the register holds every target whose
-// stride is below run_min and is grown towards longer contiguous runs (>= 256 amplitudes) while
-// the tile (dH runs of BL amplitudes) fits the LDS budget. Returns false when no target is low
+// stride is below run_min and is grown towards longer contiguous runs while the tile (dH runs of
+// BL amplitudes) fits the LDS budget. Returns false when no target is low
 // (the direct kernel applies) or the tile would not fit.
 bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) {
   const TuneParams& tp = tune();
@@ -351,8 +391,9 @@ bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) 
   for (int j = 0; j < p.k; ++j)
     if (r.strides[p.targets[j]] < tp.run_min) low_idx = std::min(low_idx, int(p.targets[j]));
   if (low_idx >= r.n) return false;
-  const uint64_t emax = uint64_t(tp.tile_elems) * (prec == QD_C128 ? 1u : 2u);
-  const uint64_t run_target = 256;
+  const uint64_t ept = prec == QD_C128 ? TileEpt<double>::value : TileEpt<float>::value;
+  const uint64_t emax = std::min<uint64_t>(uint64_t(tp.tile_elems) * (prec == QD_C128 ? 1u : 2u),
+                                           uint64_t(tp.tile_block) * ept);
   bool is_t[QD_MAX_QUDITS] = {};
   for (int j = 0; j < p.k; ++j) is_t[p.targets[j]] = true;
   int pq = low_idx;
@@ -360,7 +401,7 @@ bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) 
   uint64_t dH = 1;
   for (int i = 0; i < pq; ++i)
     if (is_t[i]) dH *= r.dims[i];
-  while (pq > 0 && BL < run_target) {
+  while (pq > 0) {
     const int q = pq - 1;
     const uint64_t nBL = BL * r.dims[q];
     const uint64_t ndH = is_t[q] ? dH / r.dims[q] : dH;
@@ -412,6 +453,7 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       a.op = op;
       a.BL = uint32_t(BL);
       a.dH = uint32_t(dH);
+      a.blm = make_magic32(uint32_t(BL));
       int64_t tbase = 0, ibase = 0;
       for (int j = 0; j < p.m; ++j) {
         const int c = p.controls[j];
@@ -471,7 +513,9 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   fill_doff<DT>(p, a.toff, a.doff);
   if (a.sm.count == 0) return QD_OK;
   const int bs = tp.direct_block;
-  if (tp.direct_spt >= 2) {
+  if (tp.direct_spt >= 4 && DT <= 4) {
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 4>), dim3(grid_for(a.sm.count, uint64_t(bs) * 4)), dim3(bs), 0, s->stream, a);
+  } else if (tp.direct_spt >= 2) {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
   } else {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0, s->stream, a);

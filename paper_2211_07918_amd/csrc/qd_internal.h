@@ -150,7 +150,9 @@ int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st
 // Readout (qd_reduce.hip)
 int launch_probabilities(const qd_state* s, double* out_dev);
 int reduce_norm2(const qd_state* s, double* out);
-int reduce_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift);
+int reduce_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift,
+                   double* norm2 = nullptr, double* fid_norm = nullptr);
+int scale_state(qd_state* s, double f);
 
 // Free-group construction: role[i] = 0 free, 1 fixed (excluded), 2 singleton (own group with
 // lmul); qudits with index < lo or >= hi are ignored (treated as excluded).

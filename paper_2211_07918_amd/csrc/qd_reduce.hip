@@ -140,7 +140,26 @@ int reduce_norm2(const qd_state* cs, double* out) {
   return QD_OK;
 }
 
-int reduce_compare(const qd_state* ref, const qd_state* cs, double* max_abs, double* fid, double* drift) {
+template <typename R>
+__global__ __launch_bounds__(256) void k_scale(R* psi, uint64_t n_reals, double f) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_reals; i += uint64_t(gridDim.x) * blockDim.x)
+    psi[i] = R(double(psi[i]) * f);
+}
+
+int scale_state(qd_state* s, double f) {
+  const uint64_t n = 2 * uint64_t(s->reg.D);
+  const unsigned grid = unsigned(std::min<uint64_t>((n + 255) / 256, 1u << 16));
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_scale<double>), dim3(grid), dim3(256), 0, s->stream, (double*)s->data, n, f);
+  else
+    hipLaunchKernelGGL((k_scale<float>), dim3(grid), dim3(256), 0, s->stream, (float*)s->data, n, f);
+  QD_HIP(hipGetLastError());
+  QD_HIP(hipStreamSynchronize(s->stream));
+  return QD_OK;
+}
+
+int reduce_compare(const qd_state* ref, const qd_state* cs, double* max_abs, double* fid, double* drift,
+                   double* norm2, double* fid_norm) {
   qd_state* s = const_cast<qd_state*>(cs);
   // the reference must be complete before s's stream reads it
   if (ref->stream != s->stream) QD_HIP(hipStreamSynchronize(ref->stream));
@@ -159,9 +178,12 @@ int reduce_compare(const qd_state* ref, const qd_state* cs, double* max_abs, dou
   double h[4];
   QD_HIP(hipMemcpyAsync(h, s->red + 4 * size_t(g), 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   QD_HIP(hipStreamSynchronize(s->stream));
+  const double ov = h[0] * h[0] + h[1] * h[1];
   if (max_abs) *max_abs = h[3];
-  if (fid) *fid = 1.0 - (h[0] * h[0] + h[1] * h[1]);
+  if (fid) *fid = 1.0 - ov;
   if (drift) *drift = std::fabs(h[2] - 1.0);
+  if (norm2) *norm2 = h[2];
+  if (fid_norm) *fid_norm = h[2] > 0.0 ? 1.0 - ov / h[2] : 1.0;
   return QD_OK;
 }
 

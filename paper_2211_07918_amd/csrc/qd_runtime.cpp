@@ -516,13 +516,36 @@ int qd_norm2(const qd_state* s, double* out) {
   return reduce_norm2(s, out);
 }
 
-int qd_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift) {
+static int check_compare_args(const qd_state* ref, const qd_state* s) {
   if (!ref || !s) return fail(QD_EINVAL, "null state");
   if (ref->prec != QD_C128) return fail(QD_EDIM, "reference state must be complex128");
   if (ref->reg.n != s->reg.n || ref->reg.D != s->reg.D) return fail(QD_EDIM, "registers differ");
   for (int i = 0; i < s->reg.n; ++i)
     if (ref->reg.dims[i] != s->reg.dims[i]) return fail(QD_EDIM, "registers differ");
+  return QD_OK;
+}
+
+int qd_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift) {
+  int rc = check_compare_args(ref, s);
+  if (rc) return rc;
   return reduce_compare(ref, s, max_abs, fid, drift);
+}
+
+int qd_compare_ex(const qd_state* ref, const qd_state* s, double* out) {
+  if (!out) return fail(QD_EINVAL, "null output");
+  int rc = check_compare_args(ref, s);
+  if (rc) return rc;
+  return reduce_compare(ref, s, &out[0], &out[1], &out[2], &out[3], &out[4]);
+}
+
+int qd_normalize(qd_state* s, double* before) {
+  if (!s) return fail(QD_EINVAL, "null state");
+  double n2 = 0.0;
+  int rc = reduce_norm2(s, &n2);
+  if (rc) return rc;
+  if (before) *before = n2;
+  if (!(n2 > 0.0) || !std::isfinite(n2)) return fail(QD_EINVAL, "state norm is zero or not finite");
+  return scale_state(s, 1.0 / std::sqrt(n2));
 }
 
 int qd_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {

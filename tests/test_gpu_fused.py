@@ -1,0 +1,226 @@
+"""GPU parity of gate fusion (qd_fuse) and fused-block application (qd_apply_fused).
+
+* Each FP64 block built on the GPU equals the oracle's product of the block's gates embedded in
+  its window, within 1e-12 (fusion is exact in exact arithmetic).
+* Fused FP64 application reproduces the oracle state within 1e-12.
+* Matrix-core modes keep the state in complex64: graded by fidelity loss 1 - |<psi64|psi32>|^2
+  <= 1e-6 against the oracle (shrunken registers) or the complex128 plain GPU path (full size),
+  with the max-abs error and norm drift reported. FP32 products round A and X to 24 bits and
+  accumulate 2B terms per output in FP32, so the 2-norm error of nb blocks stays below
+  4 nb (2B) 2^-24; split BF16 represents A and X to ~16 bits, giving 3 * 2^-16 per product.
+"""
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+import paper_2211_07918_amd as Q
+from gpu_util import fidelity_loss, max_abs, torch_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stream():
+    return torch_stream()
+
+
+def fuse(circ, maxb, stream):
+    ga = Q.GateArray(circ.gates, lambda i: circ.dims)
+    return Q.qd_fuse(circ.dims, ga, maxb, stream)
+
+
+def blocks_of(f):
+    return [Q.qd_fused_block_info(f, b) for b in range(Q.qd_fused_count(f))]
+
+
+def run_fused(circ, f, prec, mode, stream):
+    s = Q.qd_state_init(circ.dims, prec, stream)
+    try:
+        if circ.init_amps is not None:
+            Q.qd_state_upload(s, circ.init_amps)
+        Q.qd_apply_fused(s, f, mode)
+        return Q.qd_state_download(s)
+    finally:
+        Q.qd_state_free(s)
+
+
+CASES = [("qft4x6", lambda: C.config2(6), 64), ("brick3x7", lambda: C.config3(7, 6), 81),
+         ("hybrid-shrink", lambda: C.config1_shrink(80), 64), ("hybrid-shrink-27", lambda: C.config1_shrink(80), 27),
+         ("qft3x6", lambda: C.Circuit((3,) * 6, C.qudit_qft_gates(3, 6),
+                                      init_amps=C.random_basis_superposition(729, 50, C.seeded_rng(3))), 81),
+         ("random-128", lambda: C.random_circuit((2, 4, 2, 2, 4, 2, 2), 40, C.seeded_rng(4), max_controls=1,
+                                                 max_dT=16), 128),
+         ("random-16", lambda: C.random_circuit((2, 3, 2, 2, 3, 2), 40, C.seeded_rng(5), max_controls=0,
+                                                max_dT=12), 16)]
+
+
+@pytest.mark.parametrize("name,make,maxb", CASES)
+def test_blocks_match_oracle_products(stream, name, make, maxb):
+    circ = make()
+    f = fuse(circ, maxb, stream)
+    try:
+        infos = blocks_of(f)
+        covered = []
+        for b, info in enumerate(infos):
+            gates = [circ.gates[i] for i in info["gates"]]
+            assert info["gates"] == sorted(info["gates"]) and info["first_gate"] == info["gates"][0]
+            covered += info["gates"]
+            win = set(q for g in gates for q in g.qudits())
+            assert sorted(win) == info["window"]
+            assert info["B"] == int(np.prod([circ.dims[q] for q in info["window"]])) <= maxb
+            M = Q.qd_fused_download_block(f, b)
+            assert max_abs(M, O.fused_block(circ.dims, info["window"], gates)) <= 1e-12, (name, b)
+        assert sorted(covered) == list(range(len(circ.gates)))
+    finally:
+        Q.qd_fused_free(f)
+
+
+@pytest.mark.parametrize("name,make,maxb", CASES)
+def test_fused_fp64_equals_oracle(stream, name, make, maxb):
+    circ = make()
+    f = fuse(circ, maxb, stream)
+    try:
+        psi = run_fused(circ, f, Q.QD_C128, Q.QD_MODE_FP64_PLAIN, stream)
+    finally:
+        Q.qd_fused_free(f)
+    assert max_abs(psi, O.run_circuit(circ)) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+@pytest.mark.parametrize("name,make,maxb", CASES)
+def test_matrix_core_modes_vs_oracle(stream, mode, name, make, maxb):
+    circ = make()
+    f = fuse(circ, maxb, stream)
+    try:
+        nb = Q.qd_fused_count(f)
+        psi = run_fused(circ, f, Q.QD_C64, mode, stream)
+    finally:
+        Q.qd_fused_free(f)
+    ref = O.run_circuit(circ)
+    n2 = float(np.vdot(psi.astype(np.complex128), psi.astype(np.complex128)).real)
+    fid = fidelity_loss(ref, psi)
+    fid_norm = 1.0 - (1.0 - fid) / n2
+    if mode == Q.QD_MODE_FP32_MFMA:
+        assert fid <= 1e-6, (name, fid)
+        assert max_abs(psi, ref) <= 4 * nb * 2 * maxb * 2.0 ** -24
+        assert abs(n2 - 1.0) <= 4 * nb * 2.0 ** -24 * 2 * maxb
+    else:
+        # two BF16 terms hold A to ~2^-16, so the norm drifts by up to ~2^-16 per block; the
+        # direction of the state is held to the FP32 bound
+        assert fid_norm <= 1e-6, (name, fid_norm)
+        assert abs(n2 - 1.0) <= 4 * nb * 2.0 ** -16, (name, n2)
+        assert max_abs(psi, ref) <= 4 * nb * 3 * 2.0 ** -16
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+def test_qft_10_ququarts_vs_oracle_and_fft(stream, mode):
+    """The qudit QFT on 10 ququarts (D = 1,048,576): fused complex64 against the oracle and
+    against sqrt(N) ifft of the input."""
+    circ = C.config2(10)
+    f = fuse(circ, 64, stream)
+    try:
+        psi = run_fused(circ, f, Q.QD_C64, mode, stream)
+    finally:
+        Q.qd_fused_free(f)
+    ref = np.sqrt(circ.D) * np.fft.ifft(circ.init_amps)
+    n2 = float(np.vdot(psi.astype(np.complex128), psi.astype(np.complex128)).real)
+    for r in (ref, O.run_circuit(circ)):
+        fid = fidelity_loss(r, psi)
+        assert (fid if mode == Q.QD_MODE_FP32_MFMA else 1.0 - (1.0 - fid) / n2) <= 1e-6, fid
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+def test_brickwork_12_qutrits_vs_oracle(stream, mode):
+    circ = C.config3(12, 30)
+    f = fuse(circ, 81, stream)
+    try:
+        psi = run_fused(circ, f, Q.QD_C64, mode, stream)
+    finally:
+        Q.qd_fused_free(f)
+    fid = fidelity_loss(O.run_circuit(circ), psi)
+    n2 = float(np.vdot(psi.astype(np.complex128), psi.astype(np.complex128)).real)
+    assert (fid if mode == Q.QD_MODE_FP32_MFMA else 1.0 - (1.0 - fid) / n2) <= 1e-6, (fid, n2)
+
+
+def _plain64(circ, stream):
+    s = Q.qd_state_init(circ.dims, Q.QD_C128, stream)
+    if circ.init_amps is not None:
+        Q.qd_state_upload(s, circ.init_amps)
+    for g in circ.gates:
+        Q.apply_circuit_gate(s, g, circ.dims)
+    return s
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+def test_qft_14_ququarts_full_size(stream, mode):
+    """D = 268,435,456: fused complex64 vs the complex128 plain GPU path, compared on the GPU in
+    FP64; plus sampled amplitudes against sqrt(N) ifft of the sparse input."""
+    circ = C.config2(14)
+    ref = _plain64(circ, stream)
+    f = fuse(circ, 64, stream)
+    s = Q.qd_state_init(circ.dims, Q.QD_C64, stream)
+    try:
+        Q.qd_state_upload(s, circ.init_amps)
+        Q.qd_apply_fused(s, f, mode)
+        cmp = Q.qd_compare_ex(ref, s)
+        key = "fid_loss" if mode == Q.QD_MODE_FP32_MFMA else "fid_loss_normalized"
+        assert cmp[key] <= 1e-6 and cmp["max_abs"] <= 1e-5, cmp
+        # the plain FP64 path itself against the closed form at sampled outputs
+        psi64 = Q.qd_state_download(ref)
+        nz = np.flatnonzero(circ.init_amps)
+        idx = C.seeded_rng(9).choice(circ.D, 64, replace=False)
+        N = circ.D
+        want = [np.sum(circ.init_amps[nz] * np.exp(2j * np.pi * (nz * int(y) % N) / N)) / np.sqrt(N) for y in idx]
+        assert max_abs(psi64[idx], np.array(want)) <= 1e-12
+    finally:
+        Q.qd_state_free(s)
+        Q.qd_state_free(ref)
+        Q.qd_fused_free(f)
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+def test_brickwork_20_qutrits_full_size(stream, mode):
+    """D = 3,486,784,401 (28 GB complex64, 56 GB complex128 comparator), 30 brickwork layers of
+    Haar 9x9 gates fused into 81x81 blocks."""
+    circ = C.config3(20, 30)
+    ref = _plain64(circ, stream)
+    f = fuse(circ, 81, stream)
+    s = Q.qd_state_init(circ.dims, Q.QD_C64, stream)
+    try:
+        Q.qd_apply_fused(s, f, mode)
+        cmp = Q.qd_compare_ex(ref, s)
+        assert cmp["fid_loss_normalized"] <= 1e-6, cmp
+        if mode == Q.QD_MODE_FP32_MFMA:
+            assert cmp["fid_loss"] <= 1e-6, cmp
+        assert abs(Q.qd_norm2(ref) - 1.0) <= 1e-12
+        # FP64 renormalisation restores Eq. (1) and leaves only the direction error
+        Q.qd_normalize(s)
+        cmp2 = Q.qd_compare_ex(ref, s)
+        assert cmp2["norm_drift"] <= 1e-6 and cmp2["fid_loss"] <= 1e-6, cmp2
+    finally:
+        Q.qd_state_free(s)
+        Q.qd_state_free(ref)
+        Q.qd_fused_free(f)
+
+
+def test_mode_and_register_errors(stream):
+    circ = C.config2(5)
+    f = fuse(circ, 64, stream)
+    try:
+        s64 = Q.qd_state_init(circ.dims, Q.QD_C128, stream)
+        s32 = Q.qd_state_init(circ.dims, Q.QD_C64, stream)
+        other = Q.qd_state_init((4,) * 4 + (2,), Q.QD_C64, stream)
+        try:
+            for s, mode in ((s64, Q.QD_MODE_FP32_MFMA), (s32, Q.QD_MODE_FP64_PLAIN), (other, Q.QD_MODE_FP32_MFMA)):
+                with pytest.raises(Q.QDError) as e:
+                    Q.qd_apply_fused(s, f, mode)
+                assert e.value.code == Q.QD_EDIM
+            with pytest.raises(Q.QDError) as e:
+                Q.qd_apply_fused(s32, f, 7)
+            assert e.value.code == Q.QD_EINVAL
+        finally:
+            for s in (s64, s32, other):
+                Q.qd_state_free(s)
+    finally:
+        Q.qd_fused_free(f)
