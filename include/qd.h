@@ -267,9 +267,10 @@ int qd_batch_offset(const qd_batch* b, int32_t c, int64_t* off_out);
 int qd_batch_reset(qd_batch* b);
 
 /* One gate layer: gate c acts on circuit c (a Moment of every circuit, Sec. 3.5). gates[c].k == 0
- * means no gate for circuit c in this layer. Supported: one target (d_t <= 16) and at most one
- * control; other shapes are QD_EINVAL. Every layer runs as one persistent launch. While capture
- * is on, the launch is recorded into the batch's graph instead of being run. */
+ * means no gate for circuit c in this layer. Supported: one target (d_t <= 8) and at most one
+ * control; other shapes are QD_EINVAL. Gates are validated as in qd_apply_gate before any device
+ * work. Every layer runs as one persistent launch. While capture is on, the launch is recorded
+ * into the batch's graph instead of being run. */
 int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
 
 /* on = 1 starts recording layers into a new graph (dropping any previous one); on = 0 ends the
