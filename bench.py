@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
+    ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--extras", default="copy,qft,brick,batch",
+                    help="comma list of extras: copy, qft, brick, batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -159,6 +163,119 @@ def bench_copy(Q, torch):
     return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def _ev(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _plain_state(Q, circ, prec, stream):
+    s = Q.qd_state_init(circ.dims, prec, stream)
+    if circ.init_amps is not None:
+        Q.qd_state_upload(s, circ.init_amps)
+    return s
+
+
+def bench_fused(Q, torch, circ, maxb, name, warm=True):
+    """Fused complex64 (FP32 and split-BF16 matrix cores) against the complex128 plain path on the
+    same circuit: time, throughput, matrix-core utilisation and the precision report."""
+    import numpy as np
+    stream = torch.cuda.current_stream().cuda_stream
+    plans = [(g.targets, g.controls, g.cvals, Q.gate_unitary(g, circ.dims)) for g in circ.gates]
+    ref = _plain_state(Q, circ, Q.QD_C128, stream)
+    e0, e1 = _ev(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for t, c, v, U in plans:
+        Q.qd_apply_gate(ref, t, c, v, U)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    t0 = time.perf_counter()
+    f = Q.qd_fuse(circ.dims, Q.GateArray(circ.gates, lambda i: circ.dims), maxb, stream)
+    fuse_s = time.perf_counter() - t0
+    nb = Q.qd_fused_count(f)
+    Bs = [Q.qd_fused_block_info(f, b)["B"] for b in range(nb)]
+    useful = float(sum(8.0 * B * circ.D for B in Bs))
+    out = {"D": circ.D, "gates": len(circ.gates), "blocks": nb, "max_block_dim": maxb, "fuse_s": fuse_s,
+           "plain_c128_ms": plain_ms, "plain_c128_amp_upd_per_s": len(circ.gates) * circ.D / (plain_ms * 1e-3)}
+    for mode, mname, peak in ((Q.QD_MODE_FP32_MFMA, "fp32_mfma", 157.3), (Q.QD_MODE_BF16X3_MFMA, "bf16x3_mfma", 2500.0 / 3)):
+        if warm:
+            s = _plain_state(Q, circ, Q.QD_C64, stream)
+            Q.qd_apply_fused(s, f, mode)        # warm-up pass (states are not reused below)
+            Q.qd_state_free(s)
+        s = _plain_state(Q, circ, Q.QD_C64, stream)
+        torch.cuda.synchronize()
+        e0.record()
+        Q.qd_apply_fused(s, f, mode)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cmp = Q.qd_compare_ex(ref, s)
+        Q.qd_normalize(s)
+        cmpn = Q.qd_compare_ex(ref, s)
+        Q.qd_state_free(s)
+        tf = useful / (ms * 1e-3) / 1e12
+        out[mname] = {"ms": ms, "ms_per_block": ms / nb, "amp_upd_per_s": len(circ.gates) * circ.D / (ms * 1e-3),
+                      "useful_TFLOPs": tf, "peak_TFLOPs": peak, "mfma_frac": tf / peak,
+                      "hbm_GBps": nb * 16.0 * circ.D / (ms * 1e-3) / 1e9,
+                      "speedup_vs_plain_c128": plain_ms / ms, "max_abs": cmp["max_abs"], "fid_loss": cmp["fid_loss"],
+                      "norm_drift": cmp["norm_drift"], "fid_loss_normalized": cmp["fid_loss_normalized"],
+                      "fid_loss_after_fp64_normalise": cmpn["fid_loss"]}
+        log(f"{name} {mname}: {ms:.1f} ms ({nb} blocks), {tf:.1f} TFLOP/s, x{plain_ms / ms:.2f} vs plain c128, "
+            f"fid_loss {cmp['fid_loss']:.2e} (normalised {cmp['fid_loss_normalized']:.2e})")
+    Q.qd_state_free(ref)
+    Q.qd_fused_free(f)
+    return out
+
+
+def bench_batch(Q, torch, ncirc=4096):
+    """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
+    layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
+    import numpy as np
+    import circuits as C
+    stream = torch.cuda.current_stream().cuda_stream
+    circs = C.config4(ncirc)
+    L = len(circs[0].gates)
+    gas = [Q.GateArray([c.gates[l] for c in circs], lambda i: circs[i].dims) for l in range(L)]
+    upd = 0
+    for c in circs:
+        for g in c.gates:
+            upd += c.D // (int(np.prod([c.dims[x] for x in g.controls])) if g.controls else 1)
+    b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C64, stream)
+    Q.qd_batch_autotune(b, gas[0])
+    block, spt = Q.qd_tune_get(Q.QD_TUNE_BATCH_BLOCK), Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT)
+    Q.qd_batch_capture(b, True)
+    for ga in gas:
+        Q.qd_batch_apply_layer(b, ga)
+    Q.qd_batch_capture(b, False)
+    Q.qd_batch_replay(b)
+    e0, e1 = _ev(torch)
+    reps = 3
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        Q.qd_batch_replay(b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    Q.qd_batch_free(b)
+    # one by one: every gate of every circuit through qd_apply_gate on its own state
+    states = [Q.qd_state_init(c.dims, Q.QD_C64, stream) for c in circs]
+    mats = [[(g.targets, g.controls, g.cvals, Q.gate_unitary(g, c.dims)) for g in c.gates] for c in circs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, m in zip(states, mats):
+        for t, cc, v, U in m:
+            Q.qd_apply_gate(s, t, cc, v, U)
+    torch.cuda.synchronize()
+    one_s = time.perf_counter() - t0
+    for s in states:
+        Q.qd_state_free(s)
+    return {"circuits": ncirc, "layers": L, "sum_D": int(sum(c.D for c in circs)), "graph_ms": ms,
+            "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
+            "hbm_GBps": 16.0 * upd / (ms * 1e-3) / 1e9, "one_by_one_s": one_s,
+            "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt}
+
+
 def bench_cpu(circ, seconds):
     """The oracle (never tuned) on the full register, gate by gate from |0...0>, on one host
     thread, until `seconds` of work are done."""
@@ -204,14 +321,35 @@ def main():
     torch.cuda.set_device(0)
     Q.load()
     circ = C.config1()
+    tuning = None
+    if not args.no_tune:
+        import tempfile
+        scratch = Q.qd_state_init(circ.dims, Q.QD_C128, torch.cuda.current_stream().cuda_stream)
+        path = os.path.join(tempfile.gettempdir(), "qd_tune_bench.json")
+        Q.qd_autotune(scratch, path)
+        Q.qd_state_free(scratch)
+        tuning = open(path).read().replace("\n", "")
+        log(f"autotuned: {tuning}")
     log(f"plain complex128: D={circ.D} gates={len(circ.gates)} steps={args.steps} warmup={args.warmup}")
     plain = bench_plain(args, Q, torch, circ)
     log(f"plain: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} amp-upd/s, "
         f"dominant {plain['roofline']['kernel']} {plain['roofline']['achieved']:.0f} GB/s")
     extras = {}
-    if not args.no_extras:
+    which = set() if args.no_extras else set(args.extras.split(","))
+    if "copy" in which:
         extras["copy_ceiling"] = bench_copy(Q, torch)
         log(f"copy ceiling: {extras['copy_ceiling']['GBps']:.0f} GB/s")
+    if "qft" in which:
+        extras["fused_qft_14_ququarts"] = bench_fused(Q, torch, C.config2(14), 64, "qft14")
+    if "brick" in which and not args.no_big:
+        extras["fused_brickwork_20_qutrits"] = bench_fused(Q, torch, C.config3(20, 30), 81, "brick20", warm=False)
+    if "batch" in which:
+        extras["batched_4096_circuits"] = bench_batch(Q, torch)
+        bb = extras["batched_4096_circuits"]
+        log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers, {bb['amp_upd_per_s']:.3e} amp-upd/s, "
+            f"x{bb['speedup_vs_one_by_one']:.1f} vs one by one")
+    if tuning:
+        extras["tuning"] = tuning
     out = {
         "metric": METRIC,
         "value": plain["value"],

@@ -200,6 +200,10 @@ int qd_fuse_plan(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g
  * Gates are validated as in qd_apply_gate. Asynchronous on hip_stream. */
 int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int32_t max_block_dim,
             void* hip_stream, qd_fused** out);
+/* max_block_dim = 0 lets qd_fuse choose the fusion width: each candidate in {16, 27, 32, 36, 48,
+ * 64, 81, 96, 128} is planned and costed as sum over blocks of max(8 B D / F, 16 D / H) with F
+ * and H the matrix-core and HBM rates of the complex64 block kernel (defaults 40 TFLOP/s and
+ * 5 TB/s); the cheapest plan is built. */
 
 /* Number of blocks, and per block: window size k, window qudits (caller array of >= 64 ints,
  * ascending), block dimension B, first member gate and member count; qd_fused_block_gates writes
@@ -277,6 +281,12 @@ int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
  * recording and instantiates the graph. */
 int qd_batch_capture(qd_batch* b, int32_t on);
 
+/* Autotuner of the batched layer kernel: times the layer `gates` (as qd_batch_apply_layer) with
+ * every candidate tile shape (threads per workgroup x slices per thread) and keeps the fastest in
+ * the process-wide tuning table (saved by qd_tune_save). The arena is saved and restored, so the
+ * states are unchanged. Not allowed while recording. Synchronises. */
+int qd_batch_autotune(qd_batch* b, const qd_gate* gates);
+
 /* Launch the recorded graph once on the batch's stream. QD_EINVAL if none is recorded. */
 int qd_batch_replay(qd_batch* b);
 
@@ -298,13 +308,20 @@ enum { QD_TUNE_DIRECT_BLOCK = 0, QD_TUNE_DIRECT_SPT = 1, QD_TUNE_TILE_BLOCK = 2,
 int qd_tune_set(int32_t param, int32_t value);
 int qd_tune_get(int32_t param, int32_t* value);
 
-/* Autotuner: times every candidate of the tile parameters on this state (its contents are
- * scrambled: use a scratch state) for single-qudit gates on each qudit, keeps the fastest, and
- * writes a JSON cache to path (NULL = no file). Synchronises. */
+/* Autotuner of the gate kernels: for each stride class of the smallest target stride (1, 2-3,
+ * 4-15, 16-255, >= 256) present in the state's register, times a dense single-qudit gate with
+ * every candidate tile shape (direct: 64/128/256 threads x 1/2/4 slices per thread; LDS tile:
+ * 512..4096 amplitudes x 128/256 threads) and keeps the fastest per (precision, stride class).
+ * The state's amplitudes are overwritten: pass a scratch state. Writes the table as JSON to path
+ * (NULL = no file). A later qd_tune_set discards the tuned table. Synchronises. */
 int qd_autotune(qd_state* scratch, const char* path);
 
-/* Load a cache written by qd_autotune. QD_EINVAL if the file cannot be parsed. */
+/* Load a cache written by qd_autotune / qd_tune_save (replacing the current table). QD_EINVAL if
+ * the file cannot be read or holds no valid entry. */
 int qd_tune_load(const char* path);
+
+/* Write the current tuning table (gate kernels and batched kernel) as JSON to path. */
+int qd_tune_save(const char* path);
 
 /* Device-to-device copy of `bytes` bytes with the library's streaming copy kernel, for the HBM
  * ceiling and the hardware-counter calibration. Asynchronous on hip_stream. */

@@ -34,7 +34,8 @@ __all__ = [
     "qd_normalize",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
     "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
-    "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_stream_copy",
+    "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_tune_save", "qd_batch_autotune",
+    "qd_stream_copy",
     "gate_unitary", "apply_circuit_gate", "GateArray",
 ]
 
@@ -120,6 +121,8 @@ _SIGS = {
     "qd_tune_get": (C.c_int, [C.c_int32, _I32P]),
     "qd_autotune": (C.c_int, [_P, C.c_char_p]),
     "qd_tune_load": (C.c_int, [C.c_char_p]),
+    "qd_tune_save": (C.c_int, [C.c_char_p]),
+    "qd_batch_autotune": (C.c_int, [_P, C.POINTER(_Gate)]),
     "qd_stream_copy": (C.c_int, [_P, _P, C.c_int64, _P]),
 }
 
@@ -492,6 +495,15 @@ def qd_autotune(scratch_state: int, path: Optional[str] = None):
 
 def qd_tune_load(path: str):
     _check(load().qd_tune_load(path.encode()))
+
+
+def qd_tune_save(path: str):
+    _check(load().qd_tune_save(path.encode()))
+
+
+def qd_batch_autotune(b: int, gates):
+    """gates: a GateArray with one slot per circuit (the layer to time)."""
+    _check(load().qd_batch_autotune(_P(b), gates.arr))
 
 
 def qd_stream_copy(dst: int, src: int, nbytes: int, stream: int = 0):

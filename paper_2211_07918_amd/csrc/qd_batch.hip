@@ -415,6 +415,52 @@ int qd_batch_download(const qd_batch* b, void* host, int64_t total) {
   return QD_OK;
 }
 
+int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
+  if (!b || !gates) return fail(QD_EINVAL, "null argument");
+  if (b->capturing) return fail(QD_EINVAL, "cannot tune while recording");
+  // the arena is saved and restored around the timed layers
+  const size_t bytes = size_t(b->total) * amp_bytes(b->prec);
+  void* save = nullptr;
+  QD_HIP(hipMalloc(&save, bytes));
+  hipError_t e = hipMemcpyAsync(save, b->arena, bytes, hipMemcpyDeviceToDevice, b->stream);
+  TuneParams& tp = tune();
+  const int old_block = tp.batch_block, old_spt = tp.batch_spt;
+  int best_block = old_block, best_spt = old_spt, rc = QD_OK;
+  float best = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int blk : {128, 256})
+    for (int spt : {1, 2, 4}) {
+      if (e != hipSuccess || rc) break;
+      tp.batch_block = blk;
+      tp.batch_spt = spt;
+      rc = qd_batch_apply_layer(b, gates);  // warm-up
+      if (!rc) e = hipEventRecord(e0, b->stream);
+      for (int i = 0; i < 3 && !rc && e == hipSuccess; ++i) rc = qd_batch_apply_layer(b, gates);
+      if (!rc && e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (!rc && e == hipSuccess && ms < best) {
+        best = ms;
+        best_block = blk;
+        best_spt = spt;
+      }
+    }
+  tp.batch_block = (rc || e != hipSuccess) ? old_block : best_block;
+  tp.batch_spt = (rc || e != hipSuccess) ? old_spt : best_spt;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  hipError_t e2 = hipMemcpyAsync(b->arena, save, bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
+  (void)hipFree(save);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "batch autotune");
+  if (e2 != hipSuccess) return hip_fail(e2, "batch autotune restore");
+  return QD_OK;
+}
+
 void qd_batch_free(qd_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);

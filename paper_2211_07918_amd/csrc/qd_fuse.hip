@@ -154,8 +154,27 @@ int qd_fuse(const int32_t* dims, int32_t n, const qd_gate* gates, int32_t g, int
   }
   std::vector<int32_t> bo;
   std::vector<FusedBlockInfo> blocks;
-  rc = plan_fusion(r, gates, g, max_block_dim, &bo, &blocks);
-  if (rc) return rc;
+  if (max_block_dim == 0) {
+    // fusion width from a cost model: matrix-core time vs HBM time per block
+    const double F = 40e12, H = 5e12, D = double(r.D);
+    double best = 1e300;
+    for (int cand : {16, 27, 32, 36, 48, 64, 81, 96, 128}) {
+      std::vector<int32_t> cbo;
+      std::vector<FusedBlockInfo> cbl;
+      if (plan_fusion(r, gates, g, cand, &cbo, &cbl) != QD_OK) continue;
+      double cost = 0.0;
+      for (const auto& bl : cbl) cost += std::max(8.0 * bl.B * D / F, 16.0 * D / H);
+      if (cost < best) {
+        best = cost;
+        bo.swap(cbo);
+        blocks.swap(cbl);
+      }
+    }
+    if (best == 1e300) return fail(QD_EDIM, "no fusion width fits the circuit's gates");
+  } else {
+    rc = plan_fusion(r, gates, g, max_block_dim, &bo, &blocks);
+    if (rc) return rc;
+  }
 
   auto* f = new qd_fused();
   f->reg = r;

@@ -387,13 +387,21 @@ static void fill_mono(const GatePlan& p, MonoOp<R, DT>* op) {
 // (the direct kernel applies) or the tile would not fit.
 bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) {
   const TuneParams& tp = tune();
-  int low_idx = r.n;
+  int64_t min_stride = INT64_MAX;
+  int min_t = -1;
+  for (int j = 0; j < p.k; ++j)
+    if (r.strides[p.targets[j]] < min_stride) {
+      min_stride = r.strides[p.targets[j]];
+      min_t = p.targets[j];
+    }
+  const TuneEntry e = entry_for(prec, min_stride);
+  if (!e.tiled) return false;
+  int low_idx = min_t;
   for (int j = 0; j < p.k; ++j)
     if (r.strides[p.targets[j]] < tp.run_min) low_idx = std::min(low_idx, int(p.targets[j]));
-  if (low_idx >= r.n) return false;
   const uint64_t ept = prec == QD_C128 ? TileEpt<double>::value : TileEpt<float>::value;
-  const uint64_t emax = std::min<uint64_t>(uint64_t(tp.tile_elems) * (prec == QD_C128 ? 1u : 2u),
-                                           uint64_t(tp.tile_block) * ept);
+  const uint64_t emax = std::min<uint64_t>(uint64_t(e.tile_elems) * (prec == QD_C128 ? 1u : 2u),
+                                           uint64_t(e.block) * ept);
   bool is_t[QD_MAX_QUDITS] = {};
   for (int j = 0; j < p.k; ++j) is_t[p.targets[j]] = true;
   int pq = low_idx;
@@ -442,8 +450,11 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   for (int j = 0; j < p.k; ++j) role[p.targets[j]] = 1;
   for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
 
+  int64_t min_stride = INT64_MAX;
+  for (int j = 0; j < p.k; ++j) min_stride = std::min<int64_t>(min_stride, r.strides[p.targets[j]]);
+  const TuneEntry ent = entry_for(s->prec, min_stride);
   TileGeom tg;
-  if (tile_geometry(r, p, sizeof(R) == 8 ? QD_C128 : QD_C64, &tg)) {
+  if (tile_geometry(r, p, s->prec, &tg)) {
     const int pq = tg.pq;
     const uint64_t BL = tg.BL, dH = tg.dH;
     {
@@ -495,7 +506,7 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       if (a.tiles.count == 0 || a.inner.count == 0) return QD_OK;
       const size_t lds = size_t(BL * dH) * sizeof(R) * 2;
       const unsigned grid = a.tiles.count;
-      hipLaunchKernelGGL((k_slices_tiled<R, DT, OP>), dim3(grid), dim3(tp.tile_block), lds, s->stream, a);
+      hipLaunchKernelGGL((k_slices_tiled<R, DT, OP>), dim3(grid), dim3(ent.block), lds, s->stream, a);
       return check_launch("k_slices_tiled");
     }
   }
@@ -512,10 +523,10 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   target_offsets(r, p, a.toff);
   fill_doff<DT>(p, a.toff, a.doff);
   if (a.sm.count == 0) return QD_OK;
-  const int bs = tp.direct_block;
-  if (tp.direct_spt >= 4 && DT <= 4) {
+  const int bs = ent.block;
+  if (ent.spt >= 4 && DT <= 4) {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 4>), dim3(grid_for(a.sm.count, uint64_t(bs) * 4)), dim3(bs), 0, s->stream, a);
-  } else if (tp.direct_spt >= 2) {
+  } else if (ent.spt >= 2) {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
   } else {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0, s->stream, a);

@@ -55,6 +55,19 @@ struct TuneParams {
 };
 TuneParams& tune();
 
+// Autotuned tile shape per (precision, stride class of the gate's smallest target stride).
+constexpr int kStrideBuckets = 5;   // strides 1 | 2-3 | 4-15 | 16-255 | >= 256
+struct TuneEntry {
+  int valid;
+  int tiled;        // stage slices in LDS
+  int block;        // threads per workgroup
+  int spt;          // slices per thread (direct kernel)
+  int tile_elems;   // LDS tile budget in complex128 amplitudes (doubled for complex64)
+};
+int stride_bucket(int64_t s);
+TuneEntry entry_for(int prec, int64_t min_stride);   // tuned entry, else the defaults above
+void clear_tuned_table();
+
 // ------------------------------------------------------------------------------------------ descriptors
 // Linear work index -> element offset: base + sum_g digit_g(idx) * stride_g, digits taken in
 // mixed radix over the groups, group 0 least significant. lmul gives each digit's weight in a

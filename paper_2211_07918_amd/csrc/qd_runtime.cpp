@@ -555,6 +555,7 @@ int qd_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) 
 }
 
 int qd_tune_set(int32_t param, int32_t value) {
+  clear_tuned_table();  // explicit settings replace an autotuned table
   TuneParams& t = tune();
   const TuneParams def;
   auto blk = [&](int v, int d) { return v == 0 ? d : v; };

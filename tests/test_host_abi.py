@@ -257,3 +257,32 @@ int main() {
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     bad, total = map(int, r.stdout.split())
     assert r.returncode == 0 and bad == 0 and total > 8_000_000
+
+
+# ------------------------------------------------------------------------------ tuning table files
+def test_tune_load_and_save(tmp_path):
+    dims = [2, 3, 4, 3, 2, 2, 3, 2, 2, 2]
+    F4 = O.f_gate(4)
+    assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_DIRECT
+    p = tmp_path / "tune.json"
+    # stride class 4 (>= 256) tiled: qudit 2 (stride 288) is staged in LDS
+    p.write_text('[\n{"prec": 0, "bucket": 4, "tiled": 1, "block": 256, "spt": 1, "tile_elems": 2048},\n'
+                 '{"batch_block": 128, "batch_spt": 4}\n]\n')
+    Q.qd_tune_load(str(p))
+    try:
+        assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_TILED
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_BLOCK) == 128 and Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT) == 4
+        out = tmp_path / "saved.json"
+        Q.qd_tune_save(str(out))
+        assert '"bucket": 4, "tiled": 1' in out.read_text()
+    finally:
+        # an explicit setting discards the tuned table and restores the defaults
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_BLOCK, 0)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT, 0)
+    assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_DIRECT
+    bad = tmp_path / "bad.json"
+    bad.write_text('[{"prec": 0, "bucket": 9, "tiled": 1, "block": 256, "spt": 1, "tile_elems": 2048}]\n')
+    with pytest.raises(Q.QDError):
+        Q.qd_tune_load(str(bad))
+    with pytest.raises(Q.QDError):
+        Q.qd_tune_load(str(tmp_path / "missing.json"))
