@@ -142,6 +142,26 @@ def bench_plain(args, Q, torch, circ):
     }
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary, if that
+    summary was taken on the current source of the gate kernels (else None)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2211_07918_amd", "csrc", "qd_gates.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
+        fields = {}
+        for line in open(path):
+            if ": " in line and not line.startswith(("#", "`", "|")):
+                k, v = line.split(": ", 1)
+                fields[k.strip()] = v.strip()
+        name = fields.get("kernel", "")
+        base = name.rsplit(",", 1)[0] + ">" if name.count("<") == 2 else name
+        if fields.get("source_sha256") == digest and base.replace(" ", "") == kernel.replace(" ", ""):
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def bench_copy(Q, torch):
     stream = torch.cuda.current_stream().cuda_stream
     nbytes = 4 << 30
@@ -332,6 +352,7 @@ def main():
         log(f"autotuned: {tuning}")
     log(f"plain complex128: D={circ.D} gates={len(circ.gates)} steps={args.steps} warmup={args.warmup}")
     plain = bench_plain(args, Q, torch, circ)
+    plain["roofline"]["traffic"] = measured_traffic(plain["roofline"]["kernel"])
     log(f"plain: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} amp-upd/s, "
         f"dominant {plain['roofline']['kernel']} {plain['roofline']['achieved']:.0f} GB/s")
     extras = {}
