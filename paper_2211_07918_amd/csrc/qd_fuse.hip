@@ -326,6 +326,8 @@ void qd_fused_free(qd_fused* f) {
     if (d.tab_hoff) (void)hipFree(d.tab_hoff);
     if (d.tab_yh) (void)hipFree(d.tab_yh);
     if (d.tab_lmap) (void)hipFree(d.tab_lmap);
+    if (d.tab_rowpos) (void)hipFree(d.tab_rowpos);
+    if (d.tab_colpos) (void)hipFree(d.tab_colpos);
   }
   delete f;
 }

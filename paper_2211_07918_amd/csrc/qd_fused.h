@@ -28,11 +28,14 @@ struct FusedArgs {
   int32_t Kp;                       // leading dimension of the A arrays (64, 128, 192 or 256)
   int32_t twoB;                     // 2B real rows in use
   uint32_t BL, dH, E, NT;           // run length, runs, amplitudes and columns per tile
+  uint32_t high_window;             // 1 if no window qudit lies inside a run (column = run offset)
   Magic32 blm;                      // division by BL
   SliceMap tiles;                   // tile index -> global offset of its first run
   const int64_t* hoff;              // dH run offsets from the tile origin
   const int32_t* yh;                // window-local index contributed by each run
   const uint32_t* lmap;             // BL entries: (column << 16) | window-local index part
+  const int32_t* rowpos;            // KPAD / 2 entries: tile position of window index y (column 0)
+  const int32_t* colpos;            // 16 NTILES entries: tile position of column n (window index 0)
 };
 
 struct FusedBlockDev {
@@ -44,6 +47,8 @@ struct FusedBlockDev {
   int64_t* tab_hoff = nullptr;
   int32_t* tab_yh = nullptr;
   uint32_t* tab_lmap = nullptr;
+  int32_t* tab_rowpos = nullptr;
+  int32_t* tab_colpos = nullptr;
   double* u64 = nullptr;            // B x B complex FP64, row-major interleaved
   float* a32 = nullptr;             // Kp x Kp real embedding, FP32
   __hip_bfloat16* ahi = nullptr;    // BF16 split of a32: hi

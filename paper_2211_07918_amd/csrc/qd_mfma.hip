@@ -43,59 +43,133 @@ __device__ __forceinline__ int64_t fm_offset(const SliceMap& sm, uint32_t idx) {
   return off;
 }
 
-// Moves the E amplitudes of a tile between HBM and the LDS column layout. TO_LDS: HBM -> LDS.
-template <bool TO_LDS>
+// Column and window-local row of tile amplitude e (run h = e / BL, offset lo inside the run).
+__device__ __forceinline__ void tile_coords(const FusedArgs& a, const int32_t* s_yh, uint32_t e, uint32_t* h,
+                                            uint32_t* lo, uint32_t* n, uint32_t* y) {
+  *h = magic_div(e, a.blm);
+  *lo = e - *h * a.BL;
+  if (a.high_window) {  // no window qudit inside the run: the run offset is the column
+    *n = *lo;
+    *y = uint32_t(s_yh[*h]);
+  } else {
+    const uint32_t lm = a.lmap[*lo];
+    *n = lm >> 16;
+    *y = uint32_t(s_yh[*h]) + (lm & 0xFFFFu);
+  }
+}
+
+// Moves the E amplitudes of a tile between HBM and the LDS column layout X[n][2y + c]
+// (TO_LDS: HBM -> LDS). A thread holds 2 CH amplitudes in flight: every HBM access of a pass is
+// issued before the first LDS access that depends on it. With an even run length a unit is two
+// adjacent amplitudes (one 16-byte access), else one amplitude (8 bytes).
+template <bool TO_LDS, int CH>
 __device__ __forceinline__ void tile_move(const FusedArgs& a, float2* __restrict__ psi, float* xs, uint32_t P,
                                           const int64_t* s_hoff, const int32_t* s_yh, int64_t g0) {
-  constexpr int CH = 8;  // amplitudes in flight per thread
+  constexpr int S = 2 * CH;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t base = 0; base < a.E; base += 256 * CH) {
-    float vr[CH], vi[CH];
-    uint32_t pos[CH];
-    int64_t goff[CH];
+  float sr[S], si[S];
+  if ((a.BL & 1u) == 0) {
+    const uint32_t units = a.E >> 1;
+    for (uint32_t base = 0; base < units; base += 256 * CH) {
+      if (!TO_LDS) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const uint32_t idx = base + tid + 256 * j;
-      pos[j] = 0xFFFFFFFFu;
-      if (idx < a.E) {
-        const uint32_t h = magic_div(idx, a.blm);
-        const uint32_t lo = idx - h * a.BL;
-        const uint32_t lm = a.lmap[lo];
-        const uint32_t n = lm >> 16, y = uint32_t(s_yh[h]) + (lm & 0xFFFFu);
-        pos[j] = n * P + 2 * y;
-        goff[j] = g0 + s_hoff[h] + lo;
-        if (TO_LDS) {
-          const float2 t = psi[goff[j]];
-          vr[j] = t.x;
-          vi[j] = t.y;
+        for (int j = 0; j < CH; ++j) {
+          const uint32_t u = base + tid + 256 * j;
+          if (u < units) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              uint32_t h, lo, n, y;
+              tile_coords(a, s_yh, 2 * u + q, &h, &lo, &n, &y);
+              const float2 t = *reinterpret_cast<const float2*>(xs + n * P + 2 * y);
+              sr[2 * j + q] = t.x;
+              si[2 * j + q] = t.y;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const uint32_t u = base + tid + 256 * j;
+        if (u < units) {
+          const uint32_t e = 2 * u;
+          const uint32_t h = magic_div(e, a.blm);
+          float4* g = reinterpret_cast<float4*>(psi + (g0 + s_hoff[h] + (e - h * a.BL)));
+          if (TO_LDS) {
+            const float4 t = *g;
+            sr[2 * j] = t.x; si[2 * j] = t.y; sr[2 * j + 1] = t.z; si[2 * j + 1] = t.w;
+          } else {
+            float4 t;
+            t.x = sr[2 * j]; t.y = si[2 * j]; t.z = sr[2 * j + 1]; t.w = si[2 * j + 1];
+            *g = t;
+          }
+        }
+      }
+      if (TO_LDS) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const uint32_t u = base + tid + 256 * j;
+          if (u < units) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              uint32_t h, lo, n, y;
+              tile_coords(a, s_yh, 2 * u + q, &h, &lo, &n, &y);
+              float2 t;
+              t.x = sr[2 * j + q];
+              t.y = si[2 * j + q];
+              *reinterpret_cast<float2*>(xs + n * P + 2 * y) = t;
+            }
+          }
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      if (pos[j] != 0xFFFFFFFFu) {
-        float2* p2 = reinterpret_cast<float2*>(xs + pos[j]);
-        if (TO_LDS) {
-          float2 t;
-          t.x = vr[j];
-          t.y = vi[j];
-          *p2 = t;
-        } else {
-          const float2 t = *p2;
-          vr[j] = t.x;
-          vi[j] = t.y;
-        }
-      }
-    }
+    return;
+  }
+  const uint32_t units = a.E;
+  for (uint32_t base = 0; base < units; base += 256 * S) {
     if (!TO_LDS) {
 #pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (pos[j] != 0xFFFFFFFFu) {
-          float2 t;
-          t.x = vr[j];
-          t.y = vi[j];
-          psi[goff[j]] = t;
+      for (int k = 0; k < S; ++k) {
+        const uint32_t u = base + tid + 256 * k;
+        if (u < units) {
+          uint32_t h, lo, n, y;
+          tile_coords(a, s_yh, u, &h, &lo, &n, &y);
+          const float2 t = *reinterpret_cast<const float2*>(xs + n * P + 2 * y);
+          sr[k] = t.x;
+          si[k] = t.y;
         }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint32_t u = base + tid + 256 * k;
+      if (u < units) {
+        const uint32_t h = magic_div(u, a.blm);
+        float2* g = psi + (g0 + s_hoff[h] + (u - h * a.BL));
+        if (TO_LDS) {
+          const float2 t = *g;
+          sr[k] = t.x;
+          si[k] = t.y;
+        } else {
+          float2 t;
+          t.x = sr[k];
+          t.y = si[k];
+          *g = t;
+        }
+      }
+    }
+    if (TO_LDS) {
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const uint32_t u = base + tid + 256 * k;
+        if (u < units) {
+          uint32_t h, lo, n, y;
+          tile_coords(a, s_yh, u, &h, &lo, &n, &y);
+          float2 t;
+          t.x = sr[k];
+          t.y = si[k];
+          *reinterpret_cast<float2*>(xs + n * P + 2 * y) = t;
+        }
+      }
     }
   }
 }
@@ -142,7 +216,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
 
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = fm_offset(a.tiles, tile);
-    tile_move<true>(a, psi, xs, P, s_hoff, s_yh, g0);
+    tile_move<true, (512 * NTILES * MTW + 511) / 512>(a, psi, xs, P, s_hoff, s_yh, g0);
     __syncthreads();
 
     v4f acc[MTW][NTILES];
@@ -194,9 +268,211 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
       }
     }
     __syncthreads();
-    tile_move<false>(a, psi, xs, P, s_hoff, s_yh, g0);
+    tile_move<false, (512 * NTILES * MTW + 511) / 512>(a, psi, xs, P, s_hoff, s_yh, g0);
     __syncthreads();
   }
+}
+
+// The tile stays in LDS in its HBM order (run h, offset lo): amplitude (window index y, column n)
+// sits at rowpos[y] + colpos[n], because the tile index is linear in the digits (window digits
+// give rowpos, the other digits of the run give colpos). The fill is a direct HBM -> LDS copy
+// (global_load_lds: no registers, every access of the tile in flight), each lane keeps the row and
+// column offsets its MFMA operands need in registers, and the drain goes through registers in
+// chunks. Padding rows (y >= B) point at a zero run after the tile, padding columns at column 0
+// (their results are discarded). WPE: waves per SIMD the register allocation must allow.
+constexpr uint32_t kRowsSlack = 2048;   // floats after the rows: tail of the last copy, padded columns
+
+template <int MTW, int NTILES, int KS, bool BF, int WPE>
+__global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
+  constexpr int KPAD = 64 * MTW;
+  constexpr int RY = KPAD / 2;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* xs = reinterpret_cast<float*>(lds_raw);
+  const uint32_t xs_floats = (a.E + a.BL) * 2 + kRowsSlack;
+  int64_t* s_hoff = reinterpret_cast<int64_t*>(xs + xs_floats);
+  int32_t* s_rowpos = reinterpret_cast<int32_t*>(s_hoff + a.dH);
+  float2* __restrict__ psi = a.psi;
+  const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+
+  for (uint32_t i = tid; i < xs_floats; i += 256) xs[i] = 0.f;
+  for (uint32_t h = tid; h < a.dH; h += 256) s_hoff[h] = a.hoff[h];
+  for (uint32_t y = tid; y < uint32_t(RY); y += 256) s_rowpos[y] = a.rowpos[y];
+  // column offsets of this lane's operands (floats); row offsets are read from LDS per K step
+  int32_t cp[NTILES];
+#pragma unroll
+  for (int nt = 0; nt < NTILES; ++nt) cp[nt] = 2 * a.colpos[16 * nt + (l & 15)];
+
+  float af[BF ? 1 : MTW][BF ? 1 : KS];
+  v8bf ahi[BF ? MTW : 1][BF ? KS : 1], alo[BF ? MTW : 1][BF ? KS : 1];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int row = 16 * (int(w) + 4 * i) + int(l & 15);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      if constexpr (BF) {
+        const int k0 = 32 * kk + 8 * int(l >> 4);
+        ahi[i][kk] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(a.ahi + size_t(row) * KPAD + k0));
+        alo[i][kk] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(a.alo + size_t(row) * KPAD + k0));
+      } else {
+        af[i][kk] = a.a32[size_t(row) * KPAD + 4 * kk + (l >> 4)];
+      }
+    }
+  }
+  __syncthreads();
+
+  const bool pair = (a.BL & 1u) == 0;
+  for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
+    const int64_t g0 = fm_offset(a.tiles, tile);
+    // ---- fill: LDS float f of the tile <- the amplitude's part in HBM (lane-consecutive LDS)
+    if (pair) {
+      const uint32_t units = a.E >> 1;  // 16 bytes: two adjacent amplitudes of one run
+      for (uint32_t u0 = w * 64; u0 < units; u0 += 256) {
+        const uint32_t u = u0 + l;
+        const float2* src = psi + g0;
+        if (u < units) {
+          const uint32_t e = 2 * u, h = magic_div(e, a.blm);
+          src = psi + (g0 + s_hoff[h] + (e - h * a.BL));
+        }
+        __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, 0);
+      }
+    } else {
+      const uint32_t units = a.E * 2;   // 4 bytes: one part of one amplitude
+      const float* pf = reinterpret_cast<const float*>(psi);
+      for (uint32_t u0 = w * 64; u0 < units; u0 += 256) {
+        const uint32_t f = u0 + l;
+        const float* src = pf + 2 * g0;
+        if (f < units) {
+          const uint32_t e = f >> 1, h = magic_div(e, a.blm);
+          src = pf + 2 * (g0 + s_hoff[h] + (e - h * a.BL)) + (f & 1u);
+        }
+        __builtin_amdgcn_global_load_lds(src, xs + u0, 4, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    v4f acc[MTW][NTILES];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int nt = 0; nt < NTILES; ++nt) acc[i][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    if constexpr (BF) {
+      // lane: column n = 16 nt + (l & 15), rows y = 16 kk + 4 (l >> 4) + 0..3 (both parts)
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        int32_t rq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rq[q] = 2 * s_rowpos[16 * kk + 4 * (l >> 4) + q];
+#pragma unroll
+        for (int nt = 0; nt < NTILES; ++nt) {
+          float xv[8];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float2 t = *reinterpret_cast<const float2*>(xs + rq[q] + cp[nt]);
+            xv[2 * q] = t.x;
+            xv[2 * q + 1] = t.y;
+          }
+          v8bf bh, bl;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const __bf16 hj = (__bf16)xv[j];
+            bh[j] = hj;
+            bl[j] = (__bf16)(xv[j] - (float)hj);
+          }
+#pragma unroll
+          for (int i = 0; i < MTW; ++i) {
+            v4f c = acc[i][nt];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i][kk], bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bh, c, 0, 0, 0);
+            acc[i][nt] = c;
+          }
+        }
+      }
+    } else {
+      // lane: column n = 16 nt + (l & 15), row y = 2 kk + (l >> 5), part c = (l >> 4) & 1
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const int32_t rk = 2 * s_rowpos[2 * kk + (l >> 5)] + ((l >> 4) & 1);
+#pragma unroll
+        for (int nt = 0; nt < NTILES; ++nt) {
+          const float b = xs[rk + cp[nt]];
+#pragma unroll
+          for (int i = 0; i < MTW; ++i)
+            acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b, acc[i][nt], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave has read X
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      const uint32_t y0 = 8 * (w + 4 * i) + 2 * (l >> 4);   // result rows 2 y0 .. 2 y0 + 3
+      const int32_t r0 = 2 * s_rowpos[y0], r1 = 2 * s_rowpos[y0 + 1];
+#pragma unroll
+      for (int nt = 0; nt < NTILES; ++nt) {
+        const uint32_t n = 16 * nt + (l & 15);
+        if (n < a.NT) {
+          float2 t;
+          if (y0 < uint32_t(a.twoB / 2)) {
+            t.x = acc[i][nt][0];
+            t.y = acc[i][nt][1];
+            *reinterpret_cast<float2*>(xs + r0 + cp[nt]) = t;
+          }
+          if (y0 + 1 < uint32_t(a.twoB / 2)) {
+            t.x = acc[i][nt][2];
+            t.y = acc[i][nt][3];
+            *reinterpret_cast<float2*>(xs + r1 + cp[nt]) = t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- drain: the tile's E amplitudes back to their runs, 8 per thread in flight
+    {
+      constexpr int CH = 8;
+      for (uint32_t base = 0; base < a.E; base += 256 * CH) {
+        float vr[CH], vi[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const uint32_t e = base + tid + 256 * j;
+          if (e < a.E) {
+            const float2 t = *reinterpret_cast<const float2*>(xs + 2 * e);
+            vr[j] = t.x;
+            vi[j] = t.y;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const uint32_t e = base + tid + 256 * j;
+          if (e < a.E) {
+            const uint32_t h = magic_div(e, a.blm);
+            float2 t;
+            t.x = vr[j];
+            t.y = vi[j];
+            psi[g0 + s_hoff[h] + (e - h * a.BL)] = t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int MTW, int NTILES, int KS, bool BF, int WPE>
+static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
+  constexpr int RY = 32 * MTW;
+  const size_t lds = ((size_t(a.E) + a.BL) * 2 + kRowsSlack) * sizeof(float) + size_t(a.dH) * sizeof(int64_t) +
+                     size_t(RY) * sizeof(int32_t);
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(cus) * per_cu));
+  auto k = k_fused_rows<MTW, NTILES, KS, BF, WPE>;
+  QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
+  QD_HIP(hipGetLastError());
+  return QD_OK;
 }
 
 template <int MTW, int NTILES, int KS, bool BF>
@@ -227,6 +503,15 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
   a.psi = reinterpret_cast<float2*>(s->data);
   if (a.tiles.count == 0) return QD_OK;
   const bool bf = mode == QD_MODE_BF16X3_MFMA;
+  if (a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
+    switch (d.variant) {
+      case 0: return bf ? launch_rows<1, 4, 2, true, 2>(a, s->stream, 3) : launch_rows<1, 4, 16, false, 2>(a, s->stream, 3);
+      case 1: return bf ? launch_rows<2, 4, 4, true, 2>(a, s->stream, 2) : launch_rows<2, 4, 32, false, 2>(a, s->stream, 2);
+      case 2: return bf ? launch_rows<3, 6, 6, true, 1>(a, s->stream, 2) : launch_rows<3, 6, 41, false, 1>(a, s->stream, 2);
+      case 3: return bf ? launch_rows<3, 6, 6, true, 1>(a, s->stream, 2) : launch_rows<3, 6, 48, false, 1>(a, s->stream, 2);
+      default: break;  // B > 96 keeps the general kernel
+    }
+  }
   switch (d.variant) {
     case 0: return bf ? launch_one<1, 4, 2, true>(a, s->stream, 3) : launch_one<1, 4, 16, false>(a, s->stream, 3);
     case 1: return bf ? launch_one<2, 4, 4, true>(a, s->stream, 2) : launch_one<2, 4, 32, false>(a, s->stream, 2);
@@ -270,6 +555,9 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
   a.E = uint32_t(BL * dH);
   a.NT = uint32_t(NT);
   a.blm = make_magic32(uint32_t(BL));
+  a.high_window = 1;
+  for (int q = pq; q < r.n; ++q)
+    if (inwin[q]) a.high_window = 0;
   // tile origins: digits of the non-window qudits above L
   int role[QD_MAX_QUDITS] = {};
   for (int q = 0; q < r.n; ++q) role[q] = inwin[q] ? 1 : 0;
@@ -317,6 +605,35 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
     }
     lmap[lo] = uint32_t(n << 16) | uint32_t(y);
   }
+  // position of amplitude (y, n) inside a tile in HBM order: rowpos[y] + colpos[n]
+  const int RY = variant_kpad(d->variant) / 2;
+  const int NC = 16 * ntiles;
+  std::vector<int32_t> rowpos(RY, int32_t(BL * dH)), colpos(NC, 0);   // padding: zero run, column 0
+  {
+    // offset inside the run of each window-local digit combination that lies in L, and of each column
+    std::vector<int64_t> y_lo(size_t(B), 0);
+    for (uint64_t lo = 0; lo < BL; ++lo) {
+      const uint32_t lm = lmap[lo];
+      const uint32_t n = lm >> 16, yl = lm & 0xFFFFu;
+      if (n == 0) y_lo[yl] = int64_t(lo);
+      if (yl == 0 && n < uint32_t(NC)) colpos[n] = int32_t(lo);
+    }
+    // y = yh[h] + yl with yl ranging over the window digits inside L: enumerate both
+    std::vector<int32_t> yl_list;
+    for (uint64_t lo = 0; lo < BL; ++lo)
+      if ((lmap[lo] >> 16) == 0) yl_list.push_back(int32_t(lmap[lo] & 0xFFFFu));
+    for (uint64_t h = 0; h < dH; ++h)
+      for (int32_t yl : yl_list) {
+        const int y = yh[h] + yl;
+        if (y < RY) rowpos[y] = int32_t(h * BL + uint64_t(y_lo[yl]));
+      }
+  }
+  QD_HIP(hipMalloc((void**)&d->tab_rowpos, sizeof(int32_t) * RY));
+  QD_HIP(hipMalloc((void**)&d->tab_colpos, sizeof(int32_t) * NC));
+  QD_HIP(hipMemcpy(d->tab_rowpos, rowpos.data(), sizeof(int32_t) * RY, hipMemcpyHostToDevice));
+  QD_HIP(hipMemcpy(d->tab_colpos, colpos.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice));
+  a.rowpos = d->variant <= 3 ? d->tab_rowpos : nullptr;
+  a.colpos = d->tab_colpos;
   QD_HIP(hipMalloc((void**)&d->tab_hoff, sizeof(int64_t) * dH));
   QD_HIP(hipMalloc((void**)&d->tab_yh, sizeof(int32_t) * dH));
   QD_HIP(hipMalloc((void**)&d->tab_lmap, sizeof(uint32_t) * BL));
