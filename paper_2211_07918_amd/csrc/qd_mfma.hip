@@ -276,31 +276,38 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
 // The tile stays in LDS in its HBM order (run h, offset lo): amplitude (window index y, column n)
 // sits at rowpos[y] + colpos[n], because the tile index is linear in the digits (window digits
 // give rowpos, the other digits of the run give colpos). The fill is a direct HBM -> LDS copy
-// (global_load_lds: no registers, every access of the tile in flight), each lane keeps the row and
-// column offsets its MFMA operands need in registers, and the drain goes through registers in
-// chunks. Padding rows (y >= B) point at a zero run after the tile, padding columns at column 0
-// (their results are discarded). WPE: waves per SIMD the register allocation must allow.
-constexpr uint32_t kRowsSlack = 2048;   // floats after the rows: tail of the last copy, padded columns
+// (global_load_lds: no registers, every access of the tile in flight), each lane keeps the column
+// offsets of its MFMA operands in registers and reads the row offsets from LDS, and the drain goes
+// through registers in batches. Padding rows (y >= B) alias row 0 and padding columns column 0:
+// the padded columns of A are zero and a result column depends on its own operand column only.
+// NH: passes over K per tile, each over NTILES / NH column tiles (fewer accumulators, so two
+// workgroups share a CU and one's copies overlap the other's products). WPE: waves per SIMD the
+// register allocation must allow.
+constexpr uint32_t kRowsSlack = 256;
+constexpr size_t kLdsBytes = 160 * 1024;   // floats after a tile: overshoot of the last 64-lane copy
 
-template <int MTW, int NTILES, int KS, bool BF, int WPE>
+__host__ __device__ inline uint32_t rows_buf_floats(uint32_t E) { return (2u * E + kRowsSlack + 3u) & ~3u; }
+
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
 __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   constexpr int KPAD = 64 * MTW;
   constexpr int RY = KPAD / 2;
+  constexpr int NTH = NTILES / NH;   // column tiles per pass over K
+  static_assert(NTILES % NH == 0, "column tiles split evenly");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* xs = reinterpret_cast<float*>(lds_raw);
-  const uint32_t xs_floats = (a.E + a.BL) * 2 + kRowsSlack;
-  int64_t* s_hoff = reinterpret_cast<int64_t*>(xs + xs_floats);
-  int32_t* s_rowpos = reinterpret_cast<int32_t*>(s_hoff + a.dH);
+  int32_t* s_rowpos = reinterpret_cast<int32_t*>(xs + rows_buf_floats(a.E));
+  int64_t* s_hoff = reinterpret_cast<int64_t*>(s_rowpos + RY);
+  uint32_t* xw = reinterpret_cast<uint32_t*>(xs);   // BF16x3: amplitude e holds (hi, lo) at words 2e, 2e + 1
   float2* __restrict__ psi = a.psi;
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
 
-  for (uint32_t i = tid; i < xs_floats; i += 256) xs[i] = 0.f;
   for (uint32_t h = tid; h < a.dH; h += 256) s_hoff[h] = a.hoff[h];
   for (uint32_t y = tid; y < uint32_t(RY); y += 256) s_rowpos[y] = a.rowpos[y];
-  // column offsets of this lane's operands (floats); row offsets are read from LDS per K step
+  // tile-local amplitude index of this lane's column in each column tile
   int32_t cp[NTILES];
 #pragma unroll
-  for (int nt = 0; nt < NTILES; ++nt) cp[nt] = 2 * a.colpos[16 * nt + (l & 15)];
+  for (int nt = 0; nt < NTILES; ++nt) cp[nt] = a.colpos[16 * nt + (l & 15)];
 
   float af[BF ? 1 : MTW][BF ? 1 : KS];
   v8bf ahi[BF ? MTW : 1][BF ? KS : 1], alo[BF ? MTW : 1][BF ? KS : 1];
@@ -321,12 +328,29 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   __syncthreads();
 
   const bool pair = (a.BL & 1u) == 0;
+  const uint32_t E = a.E;
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = fm_offset(a.tiles, tile);
-    // ---- fill: LDS float f of the tile <- the amplitude's part in HBM (lane-consecutive LDS)
+    // ---- fill: LDS float f of the tile <- the amplitude's part in HBM (lane-consecutive LDS).
+    // Batches of 8 copies per wave without bounds tests, so their run-offset lookups overlap.
     if (pair) {
-      const uint32_t units = a.E >> 1;  // 16 bytes: two adjacent amplitudes of one run
-      for (uint32_t u0 = w * 64; u0 < units; u0 += 256) {
+      const uint32_t units = E >> 1;  // 16 bytes: two adjacent amplitudes of one run
+      uint32_t u0 = w * 64;
+      for (; u0 + 256 * 7 + 64 <= units; u0 += 256 * 8) {
+        int64_t ho[8];
+        uint32_t lo[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t e = 2 * (u0 + 256 * j + l), h = magic_div(e, a.blm);
+          ho[j] = s_hoff[h];
+          lo[j] = e - h * a.BL;
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the 8 lookups are in flight together
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          __builtin_amdgcn_global_load_lds(psi + (g0 + ho[j] + lo[j]), xs + 4 * (u0 + 256 * j), 16, 0, 0);
+      }
+      for (; u0 < units; u0 += 256) {
         const uint32_t u = u0 + l;
         const float2* src = psi + g0;
         if (u < units) {
@@ -336,9 +360,24 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, 0);
       }
     } else {
-      const uint32_t units = a.E * 2;   // 4 bytes: one part of one amplitude
+      const uint32_t units = E * 2;   // 4 bytes: one part of one amplitude
       const float* pf = reinterpret_cast<const float*>(psi);
-      for (uint32_t u0 = w * 64; u0 < units; u0 += 256) {
+      uint32_t u0 = w * 64;
+      for (; u0 + 256 * 7 + 64 <= units; u0 += 256 * 8) {
+        int64_t ho[8];
+        uint32_t lo[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t f = u0 + 256 * j + l, e = f >> 1, h = magic_div(e, a.blm);
+          ho[j] = s_hoff[h];
+          lo[j] = 2 * (e - h * a.BL) + (f & 1u);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the 8 lookups are in flight together
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          __builtin_amdgcn_global_load_lds(pf + (2 * (g0 + ho[j]) + lo[j]), xs + u0 + 256 * j, 4, 0, 0);
+      }
+      for (; u0 < units; u0 += 256) {
         const uint32_t f = u0 + l;
         const float* src = pf + 2 * g0;
         if (f < units) {
@@ -351,124 +390,170 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    v4f acc[MTW][NTILES];
-#pragma unroll
-    for (int i = 0; i < MTW; ++i)
-#pragma unroll
-      for (int nt = 0; nt < NTILES; ++nt) acc[i][nt] = v4f{0.f, 0.f, 0.f, 0.f};
-
     if constexpr (BF) {
-      // lane: column n = 16 nt + (l & 15), rows y = 16 kk + 4 (l >> 4) + 0..3 (both parts)
+      // split every amplitude once, x = hi + lo in BF16, in place: (re, im) pairs of hi, then of lo
+      auto split1 = [&](uint32_t e) {
+        const float2 v = *reinterpret_cast<const float2*>(xs + 2 * e);
+        const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
+        const __bf16 lr = (__bf16)(v.x - (float)hr), li = (__bf16)(v.y - (float)hi);
+        uint2 o;
+        o.x = uint32_t(__builtin_bit_cast(uint16_t, hr)) | (uint32_t(__builtin_bit_cast(uint16_t, hi)) << 16);
+        o.y = uint32_t(__builtin_bit_cast(uint16_t, lr)) | (uint32_t(__builtin_bit_cast(uint16_t, li)) << 16);
+        *reinterpret_cast<uint2*>(xw + 2 * e) = o;
+      };
+      uint32_t base = 0;
+      for (; base + 256 * 4 <= E; base += 256 * 4) {
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        int32_t rq[4];
+        for (int j = 0; j < 4; ++j) split1(base + tid + 256 * j);
+      }
+      for (uint32_t e = base + tid; e < E; e += 256) split1(e);
+      __syncthreads();
+    }
+
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rq[q] = 2 * s_rowpos[16 * kk + 4 * (l >> 4) + q];
+    for (int hf = 0; hf < NH; ++hf) {
+      v4f acc[MTW][NTH];
 #pragma unroll
-        for (int nt = 0; nt < NTILES; ++nt) {
-          float xv[8];
+      for (int i = 0; i < MTW; ++i)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float2 t = *reinterpret_cast<const float2*>(xs + rq[q] + cp[nt]);
-            xv[2 * q] = t.x;
-            xv[2 * q + 1] = t.y;
-          }
-          v8bf bh, bl;
+        for (int t = 0; t < NTH; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+      if constexpr (BF) {
+        // lane: column n = 16 nt + (l & 15), rows y = 16 kk + 4 (l >> 4) + q, q = 0..3 (both parts).
+        // Operand group g = (kk, t) is loaded one group ahead of its products (scheduling barriers
+        // keep that order); the rows of K step kk + 1 are read at the start of K step kk.
+        constexpr int G = KS * NTH;
+        const int32_t* rpl = s_rowpos + 4 * (l >> 4);
+        int4 rq[2];
+        rq[0] = *reinterpret_cast<const int4*>(rpl);
+        uint4 oh[2], ol[2];
+        auto load_group = [&](int g) {
+          const int kk = g / NTH, nt = hf * NTH + g % NTH;
+          const int4 r = rq[kk & 1];
+          const int c = cp[nt];
+          uint4 h, lo;
+          h.x = xw[2 * (r.x + c)]; h.y = xw[2 * (r.y + c)]; h.z = xw[2 * (r.z + c)]; h.w = xw[2 * (r.w + c)];
+          lo.x = xw[2 * (r.x + c) + 1]; lo.y = xw[2 * (r.y + c) + 1];
+          lo.z = xw[2 * (r.z + c) + 1]; lo.w = xw[2 * (r.w + c) + 1];
+          oh[g & 1] = h;
+          ol[g & 1] = lo;
+        };
+        load_group(0);
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const __bf16 hj = (__bf16)xv[j];
-            bh[j] = hj;
-            bl[j] = (__bf16)(xv[j] - (float)hj);
-          }
+        for (int g = 0; g < G; ++g) {
+          const int kk = g / NTH, t = g % NTH;
+          if (t == 0 && kk + 1 < KS) rq[(kk + 1) & 1] = *reinterpret_cast<const int4*>(rpl + 16 * (kk + 1));
+          if (g + 1 < G) load_group(g + 1);
+          __builtin_amdgcn_sched_barrier(0);
+          const v8bf bh = __builtin_bit_cast(v8bf, oh[g & 1]);
+          const v8bf bl = __builtin_bit_cast(v8bf, ol[g & 1]);
 #pragma unroll
           for (int i = 0; i < MTW; ++i) {
-            v4f c = acc[i][nt];
+            v4f c = acc[i][t];
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i][kk], bh, c, 0, 0, 0);
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bl, c, 0, 0, 0);
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bh, c, 0, 0, 0);
-            acc[i][nt] = c;
+            acc[i][t] = c;
           }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        // lane: column n = 16 nt + (l & 15), row y = 2 kk + (l >> 5), part c = (l >> 4) & 1.
+        // The operands of K step kk + 1 are loaded before the products of step kk (scheduling
+        // barriers keep that order).
+        const float* xl = xs + ((l >> 4) & 1);
+        const int32_t* rpl = s_rowpos + (l >> 5);
+        float b[2][NTH];
+        int32_t rk = 2 * rpl[0];
+#pragma unroll
+        for (int t = 0; t < NTH; ++t) b[0][t] = xl[rk + 2 * cp[hf * NTH + t]];
+        rk = 2 * rpl[2];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+          if (kk + 1 < KS) {
+#pragma unroll
+            for (int t = 0; t < NTH; ++t) b[(kk + 1) & 1][t] = xl[rk + 2 * cp[hf * NTH + t]];
+            if (kk + 2 < KS) rk = 2 * rpl[2 * (kk + 2)];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int t = 0; t < NTH; ++t)
+#pragma unroll
+            for (int i = 0; i < MTW; ++i)
+              acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b[kk & 1][t], acc[i][t], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
-    } else {
-      // lane: column n = 16 nt + (l & 15), row y = 2 kk + (l >> 5), part c = (l >> 4) & 1
+      __syncthreads();  // every wave has read the operands of these columns
+      // results of these columns over their own operands (other columns are not touched)
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        const int32_t rk = 2 * s_rowpos[2 * kk + (l >> 5)] + ((l >> 4) & 1);
+      for (int i = 0; i < MTW; ++i) {
+        const uint32_t y0 = 8 * (w + 4 * i) + 2 * (l >> 4);   // result rows 2 y0 .. 2 y0 + 3
+        const int32_t r0 = 2 * s_rowpos[y0], r1 = 2 * s_rowpos[y0 + 1];
 #pragma unroll
-        for (int nt = 0; nt < NTILES; ++nt) {
-          const float b = xs[rk + cp[nt]];
-#pragma unroll
-          for (int i = 0; i < MTW; ++i)
-            acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b, acc[i][nt], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();  // every wave has read X
-#pragma unroll
-    for (int i = 0; i < MTW; ++i) {
-      const uint32_t y0 = 8 * (w + 4 * i) + 2 * (l >> 4);   // result rows 2 y0 .. 2 y0 + 3
-      const int32_t r0 = 2 * s_rowpos[y0], r1 = 2 * s_rowpos[y0 + 1];
-#pragma unroll
-      for (int nt = 0; nt < NTILES; ++nt) {
-        const uint32_t n = 16 * nt + (l & 15);
-        if (n < a.NT) {
-          float2 t;
-          if (y0 < uint32_t(a.twoB / 2)) {
-            t.x = acc[i][nt][0];
-            t.y = acc[i][nt][1];
-            *reinterpret_cast<float2*>(xs + r0 + cp[nt]) = t;
-          }
-          if (y0 + 1 < uint32_t(a.twoB / 2)) {
-            t.x = acc[i][nt][2];
-            t.y = acc[i][nt][3];
-            *reinterpret_cast<float2*>(xs + r1 + cp[nt]) = t;
+        for (int t = 0; t < NTH; ++t) {
+          const int nt = hf * NTH + t;
+          const uint32_t n = 16 * nt + (l & 15);
+          if (n < a.NT) {
+            float2 v;
+            if (y0 < uint32_t(a.twoB / 2)) {
+              v.x = acc[i][t][0];
+              v.y = acc[i][t][1];
+              *reinterpret_cast<float2*>(xs + r0 + 2 * cp[nt]) = v;
+            }
+            if (y0 + 1 < uint32_t(a.twoB / 2)) {
+              v.x = acc[i][t][2];
+              v.y = acc[i][t][3];
+              *reinterpret_cast<float2*>(xs + r1 + 2 * cp[nt]) = v;
+            }
           }
         }
       }
     }
     __syncthreads();
-    // ---- drain: the tile's E amplitudes back to their runs, 8 per thread in flight
+    // ---- drain: the tile's E amplitudes back to their runs, batches of 8 per thread in flight
     {
       constexpr int CH = 8;
-      for (uint32_t base = 0; base < a.E; base += 256 * CH) {
-        float vr[CH], vi[CH];
+      auto store1 = [&](uint32_t e, float2 v) {
+        const uint32_t h = magic_div(e, a.blm);
+        psi[g0 + s_hoff[h] + (e - h * a.BL)] = v;
+      };
+      uint32_t base = 0;
+      for (; base + 256 * CH <= E; base += 256 * CH) {
+        float2 v[CH];
+        int64_t ho[CH];
+        uint32_t lo[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-          const uint32_t e = base + tid + 256 * j;
-          if (e < a.E) {
-            const float2 t = *reinterpret_cast<const float2*>(xs + 2 * e);
-            vr[j] = t.x;
-            vi[j] = t.y;
-          }
+          const uint32_t e = base + tid + 256 * j, h = magic_div(e, a.blm);
+          v[j] = *reinterpret_cast<const float2*>(xs + 2 * e);
+          ho[j] = s_hoff[h];
+          lo[j] = e - h * a.BL;
         }
+        __builtin_amdgcn_sched_barrier(0);   // all LDS reads of the batch are in flight together
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-          const uint32_t e = base + tid + 256 * j;
-          if (e < a.E) {
-            const uint32_t h = magic_div(e, a.blm);
-            float2 t;
-            t.x = vr[j];
-            t.y = vi[j];
-            psi[g0 + s_hoff[h] + (e - h * a.BL)] = t;
-          }
-        }
+        for (int j = 0; j < CH; ++j) psi[g0 + ho[j] + lo[j]] = v[j];
       }
+      for (uint32_t e = base + tid; e < E; e += 256) store1(e, *reinterpret_cast<const float2*>(xs + 2 * e));
     }
     __syncthreads();
   }
 }
 
-template <int MTW, int NTILES, int KS, bool BF, int WPE>
+static size_t rows_lds(const FusedArgs& a, int ry) {
+  return size_t(rows_buf_floats(a.E)) * sizeof(float) + size_t(ry) * sizeof(int32_t) + size_t(a.dH) * sizeof(int64_t);
+}
+
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
 static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
   constexpr int RY = 32 * MTW;
-  const size_t lds = ((size_t(a.E) + a.BL) * 2 + kRowsSlack) * sizeof(float) + size_t(a.dH) * sizeof(int64_t) +
-                     size_t(RY) * sizeof(int32_t);
+  const size_t lds = rows_lds(a, RY);
+  if (lds > kLdsBytes) return fail(QD_EINVAL, "fused tile exceeds the LDS of a CU");
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(cus) * per_cu));
-  auto k = k_fused_rows<MTW, NTILES, KS, BF, WPE>;
+  auto k = k_fused_rows<MTW, NTILES, NH, KS, BF, WPE>;
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
   QD_HIP(hipGetLastError());
@@ -505,10 +590,14 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
   const bool bf = mode == QD_MODE_BF16X3_MFMA;
   if (a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
     switch (d.variant) {
-      case 0: return bf ? launch_rows<1, 4, 2, true, 2>(a, s->stream, 3) : launch_rows<1, 4, 16, false, 2>(a, s->stream, 3);
-      case 1: return bf ? launch_rows<2, 4, 4, true, 2>(a, s->stream, 2) : launch_rows<2, 4, 32, false, 2>(a, s->stream, 2);
-      case 2: return bf ? launch_rows<3, 6, 6, true, 1>(a, s->stream, 2) : launch_rows<3, 6, 41, false, 1>(a, s->stream, 2);
-      case 3: return bf ? launch_rows<3, 6, 6, true, 1>(a, s->stream, 2) : launch_rows<3, 6, 48, false, 1>(a, s->stream, 2);
+      case 0: return bf ? launch_rows<1, 4, 1, 2, true, 2>(a, s->stream, 3)
+                        : launch_rows<1, 4, 1, 16, false, 2>(a, s->stream, 3);
+      case 1: return bf ? launch_rows<2, 4, 1, 4, true, 2>(a, s->stream, 2)
+                        : launch_rows<2, 4, 1, 32, false, 2>(a, s->stream, 2);
+      case 2: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
+                        : launch_rows<3, 6, 2, 41, false, 2>(a, s->stream, 2);
+      case 3: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
+                        : launch_rows<3, 6, 2, 48, false, 2>(a, s->stream, 2);
       default: break;  // B > 96 keeps the general kernel
     }
   }
@@ -608,7 +697,7 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
   // position of amplitude (y, n) inside a tile in HBM order: rowpos[y] + colpos[n]
   const int RY = variant_kpad(d->variant) / 2;
   const int NC = 16 * ntiles;
-  std::vector<int32_t> rowpos(RY, int32_t(BL * dH)), colpos(NC, 0);   // padding: zero run, column 0
+  std::vector<int32_t> rowpos(RY, 0), colpos(NC, 0);   // padding rows and columns alias the first
   {
     // offset inside the run of each window-local digit combination that lies in L, and of each column
     std::vector<int64_t> y_lo(size_t(B), 0);
