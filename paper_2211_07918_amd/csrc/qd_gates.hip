@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "qd_internal.h"
+#include "qd_stream.h"
 
 namespace qd {
 
@@ -83,8 +84,15 @@ template <typename R, int DT> struct MonoOp { R ph[2 * DT]; int32_t dst[DT]; };
 // doff[c] = toff[dst[c]] for monomial gates (filled by the host so no kernel indexes its
 // arguments with a run-time value); unused by dense gates.
 
-template <typename C, typename R, int DT, typename P>
-__device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t* toff, const int64_t*,
+// put: a result into the state in HBM (ST: streaming store) or into LDS
+template <bool ST, typename C>
+__device__ __forceinline__ void put(C* p, int64_t i, C v) {
+  if constexpr (ST) st_stream(p + i, v);
+  else p[i] = v;
+}
+
+template <bool ST, typename C, typename R, int DT>
+__device__ __forceinline__ void mix_store(C* p, int64_t base, const int64_t* toff, const int64_t*,
                                           const DenseOp<R, DT>& op, const C (&x)[DT]) {
 #pragma unroll
   for (int r = 0; r < DT; ++r) {
@@ -100,12 +108,12 @@ __device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t* toff
     C y;
     y.x = re;
     y.y = im;
-    p[base + toff[r]] = y;
+    put<ST>(p, base + toff[r], y);
   }
 }
 
-template <typename C, typename R, int DT, typename P>
-__device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t*, const int64_t* doff,
+template <bool ST, typename C, typename R, int DT>
+__device__ __forceinline__ void mix_store(C* p, int64_t base, const int64_t*, const int64_t* doff,
                                           const MonoOp<R, DT>& op, const C (&x)[DT]) {
 #pragma unroll
   for (int c = 0; c < DT; ++c) {
@@ -113,7 +121,7 @@ __device__ __forceinline__ void mix_store(P p, int64_t base, const int64_t*, con
     C y;
     y.x = fma(pr, x[c].x, -pi * x[c].y);
     y.y = fma(pr, x[c].y, pi * x[c].x);
-    p[base + doff[c]] = y;
+    put<ST>(p, base + doff[c], y);
   }
 }
 
@@ -144,11 +152,11 @@ __global__ __launch_bounds__(256) void k_slices_direct(DirectArgs<R, DT, OP> a) 
   for (int s = 0; s < SPT; ++s)
     if (base[s] >= 0) {
 #pragma unroll
-      for (int y = 0; y < DT; ++y) x[s][y] = psi[base[s] + a.toff[y]];
+      for (int y = 0; y < DT; ++y) x[s][y] = ld_stream(psi + base[s] + a.toff[y]);
     }
 #pragma unroll
   for (int s = 0; s < SPT; ++s)
-    if (base[s] >= 0) mix_store<C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
+    if (base[s] >= 0) mix_store<true, C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
 }
 
 // ------------------------------------------------------------------------------------------ tiled
@@ -195,7 +203,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
       const uint32_t idx = tid + e * bs;
       if (idx < E) {
         const uint32_t h = magic_div(idx, a.blm);
-        const C t = psi[g0 + s_hoff[h] + (idx - h * a.BL)];
+        const C t = ld_stream(psi + (g0 + s_hoff[h] + (idx - h * a.BL)));
         vr[e] = t.x;
         vi[e] = t.y;
       }
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
       C x[DT];
 #pragma unroll
       for (int y = 0; y < DT; ++y) x[y] = lds[b + a.toff[y]];
-      mix_store<C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
+      mix_store<false, C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
     }
     __syncthreads();
 #pragma unroll
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
         C t;
         t.x = vr[e];
         t.y = vi[e];
-        psi[g0 + s_hoff[h] + (idx - h * a.BL)] = t;
+        st_stream(psi + (g0 + s_hoff[h] + (idx - h * a.BL)), t);
       }
     }
     if (tile + gridDim.x < a.tiles.count) __syncthreads();
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs<R> a) {
   }
 #pragma unroll
   for (int s = 0; s < SPT; ++s)
-    if (off[s] >= 0) x[s] = psi[off[s]];
+    if (off[s] >= 0) x[s] = ld_stream(psi + off[s]);
 #pragma unroll
   for (int s = 0; s < SPT; ++s)
     if (off[s] >= 0) {
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs<R> a) {
       C y;
       y.x = fma(pr, x[s].x, -pi * x[s].y);
       y.y = fma(pr, x[s].y, pi * x[s].x);
-      psi[off[s]] = y;
+      st_stream(psi + off[s], y);
     }
 }
 
@@ -300,7 +308,7 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
   for (uint64_t s0 = uint64_t(blockIdx.x) * nsw; s0 < h.sm.count; s0 += uint64_t(gridDim.x) * nsw) {
     for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
       const uint32_t j = e / dT, y = e - j * dT;
-      if (s0 + j < h.sm.count) xs[e] = psi[sm64_offset(h.sm, s0 + j) + toff[y]];
+      if (s0 + j < h.sm.count) xs[e] = ld_stream(psi + (sm64_offset(h.sm, s0 + j) + toff[y]));
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -318,7 +326,7 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
       C y;
       y.x = re;
       y.y = im;
-      psi[sm64_offset(h.sm, s0 + j) + toff[row]] = y;
+      st_stream(psi + (sm64_offset(h.sm, s0 + j) + toff[row]), y);
     }
     __syncthreads();
   }
@@ -337,9 +345,11 @@ __global__ __launch_bounds__(256) void k_fill_basis(R* psi_raw, uint64_t D, uint
   }
 }
 
+// HBM copy ceiling: one streaming 16-byte load and store per thread (the fastest copy form
+// measured on gfx950, ahead of grid-stride loops and of several accesses per thread)
 __global__ __launch_bounds__(256) void k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += uint64_t(gridDim.x) * blockDim.x)
-    dst[i] = src[i];
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n16) st_stream(dst + i, ld_stream(src + i));
 }
 
 // ------------------------------------------------------------------------------------------ launch helpers
@@ -652,11 +662,15 @@ int launch_fill_basis(qd_state* s, int64_t index) {
 
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
   const uint64_t n16 = uint64_t(bytes) / 16;
-  if (n16 == 0) return QD_OK;
-  const unsigned grid = unsigned(std::min<uint64_t>((n16 + 255) / 256, 1u << 20));
-  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint4*>(dst),
-                     reinterpret_cast<const uint4*>(src), n16);
-  return check_launch("k_stream_copy");
+  constexpr uint64_t kChunk = uint64_t(1) << 30;   // 16-byte units per launch (one per thread)
+  for (uint64_t o = 0; o < n16; o += kChunk) {
+    const uint64_t n = std::min(kChunk, n16 - o);
+    hipLaunchKernelGGL(k_stream_copy, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint4*>(dst) + o, reinterpret_cast<const uint4*>(src) + o, n);
+    const int rc = check_launch("k_stream_copy");
+    if (rc) return rc;
+  }
+  return QD_OK;
 }
 
 }  // namespace qd

@@ -22,6 +22,7 @@
 #include <cstring>
 
 #include "qd_fused.h"
+#include "qd_stream.h"
 
 namespace qd {
 
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
 // workgroups share a CU and one's copies overlap the other's products). WPE: waves per SIMD the
 // register allocation must allow.
 constexpr uint32_t kRowsSlack = 256;
+constexpr int kNt = 2;   // cache policy of the tile copies: nontemporal (the state streams through)
 constexpr size_t kLdsBytes = 160 * 1024;   // floats after a tile: overshoot of the last 64-lane copy
 
 __host__ __device__ inline uint32_t rows_buf_floats(uint32_t E) { return (2u * E + kRowsSlack + 3u) & ~3u; }
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         __builtin_amdgcn_sched_barrier(0);   // the 8 lookups are in flight together
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          __builtin_amdgcn_global_load_lds(psi + (g0 + ho[j] + lo[j]), xs + 4 * (u0 + 256 * j), 16, 0, 0);
+          __builtin_amdgcn_global_load_lds(psi + (g0 + ho[j] + lo[j]), xs + 4 * (u0 + 256 * j), 16, 0, kNt);
       }
       for (; u0 < units; u0 += 256) {
         const uint32_t u = u0 + l;
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
           const uint32_t e = 2 * u, h = magic_div(e, a.blm);
           src = psi + (g0 + s_hoff[h] + (e - h * a.BL));
         }
-        __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, kNt);
       }
     } else {
       const uint32_t units = E * 2;   // 4 bytes: one part of one amplitude
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         __builtin_amdgcn_sched_barrier(0);   // the 8 lookups are in flight together
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          __builtin_amdgcn_global_load_lds(pf + (2 * (g0 + ho[j]) + lo[j]), xs + u0 + 256 * j, 4, 0, 0);
+          __builtin_amdgcn_global_load_lds(pf + (2 * (g0 + ho[j]) + lo[j]), xs + u0 + 256 * j, 4, 0, kNt);
       }
       for (; u0 < units; u0 += 256) {
         const uint32_t f = u0 + l;
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
           const uint32_t e = f >> 1, h = magic_div(e, a.blm);
           src = pf + 2 * (g0 + s_hoff[h] + (e - h * a.BL)) + (f & 1u);
         }
-        __builtin_amdgcn_global_load_lds(src, xs + u0, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(src, xs + u0, 4, 0, kNt);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
       constexpr int CH = 8;
       auto store1 = [&](uint32_t e, float2 v) {
         const uint32_t h = magic_div(e, a.blm);
-        psi[g0 + s_hoff[h] + (e - h * a.BL)] = v;
+        st_stream(psi + (g0 + s_hoff[h] + (e - h * a.BL)), v);
       };
       uint32_t base = 0;
       for (; base + 256 * CH <= E; base += 256 * CH) {
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         }
         __builtin_amdgcn_sched_barrier(0);   // all LDS reads of the batch are in flight together
 #pragma unroll
-        for (int j = 0; j < CH; ++j) psi[g0 + ho[j] + lo[j]] = v[j];
+        for (int j = 0; j < CH; ++j) st_stream(psi + (g0 + ho[j] + lo[j]), v[j]);
       }
       for (uint32_t e = base + tid; e < E; e += 256) store1(e, *reinterpret_cast<const float2*>(xs + 2 * e));
     }
