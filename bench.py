@@ -296,34 +296,46 @@ def bench_batch(Q, torch, ncirc=4096):
             "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt}
 
 
-def bench_cpu(circ, seconds):
-    """The oracle (never tuned) on the full register, gate by gate from |0...0>, on one host
-    thread, until `seconds` of work are done."""
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - Linux has it
+        affinity = os.cpu_count()
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "affinity_cpus": affinity}
+
+
+def bench_cpu(circ, seconds, threads=1):
+    """The oracle (never tuned) on the full register, gate by gate from |0...0>, with `threads`
+    BLAS threads, until `seconds` of work are done."""
     import numpy as np
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover - threadpoolctl is installed
-        limiter = None
-    dims = circ.dims
-    psi = O.basis_state(dims)
-    upd = 0
-    n = 0
-    t0 = time.perf_counter()
-    for g in circ.gates:
-        psi = O.apply_gate(psi, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
-        dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
-        upd += circ.D // dc
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": upd / dt, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=threads):
+        dims = circ.dims
+        psi = O.basis_state(dims)
+        upd = 0
+        n = 0
+        t0 = time.perf_counter()
+        for g in circ.gates:
+            psi = O.apply_gate(psi, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+            dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
+            upd += circ.D // dc
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "amplitude-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of {len(circ.gates)} gates of the same workload at full size "
-                      f"(D={circ.D}), NumPy complex128 contraction, 1 BLAS thread, {dt:.1f} s"}
+                      f"(D={circ.D}), NumPy complex128 contraction, {threads} BLAS thread(s), {dt:.1f} s"}
 
 
 def main():
@@ -394,8 +406,16 @@ def main():
         "kernels": plain["kernels"],
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = bench_cpu(circ, args.cpu_seconds)
-        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} amp-upd/s")
+        host = host_info()
+        out["cpu_baseline"] = bench_cpu(circ, args.cpu_seconds, 1)
+        out["cpu_baseline"]["host"] = host
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} amp-upd/s on 1 thread ({host['cpu_model']})")
+        # the same oracle with a BLAS thread per CPU this process may use (context, not the baseline)
+        ncpu = max(1, min(host["affinity_cpus"] or 1, 64))
+        if ncpu > 1:
+            allc = bench_cpu(circ, args.cpu_seconds, ncpu)
+            extras["cpu_oracle_all_cores"] = allc
+            log(f"cpu oracle: {allc['value']:.3e} amp-upd/s on {ncpu} threads")
     if extras:
         out["extras"] = extras
     print(json.dumps(out), flush=True)
