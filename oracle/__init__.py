@@ -10,6 +10,9 @@ Two independent forms of the same definition are provided:
     states, multiplied together and applied to the initial state at the end, which is the paper's
     own execution scheme (Sec. 3.6: Kronecker product per Moment, operator products, final
     matrix-vector product).
+
+``oracle.measure`` holds the readout after the gates: shots of a computational-basis measurement,
+per-qudit marginals and the list of states with non-zero probability (ket output).
 """
 from .qudit import *  # noqa: F401,F403
 from .qudit import __all__  # noqa: F401
