@@ -256,6 +256,38 @@ int qd_compare_ex(const qd_state* ref64, const qd_state* s, double* out5);
  * zero or not finite (the state is left untouched). Synchronises. */
 int qd_normalize(qd_state* s, double* norm2_before);
 
+/* ---------------------------------------------------------------- measurement (Sec. 2.2, 3.1, 3.8) */
+
+/* Shots of a computational-basis measurement of every qudit (measure_all, Sec. 3.1; each qudit
+ * returns an integer digit, Sec. 2.2): out[j] is the basis index drawn by the 64-bit random word
+ * rand[j]. Outcome x has weight w_x = round(p_x 2^62), p_x = re*re + im*im in FP64 (products
+ * rounded before the sum); with W = sum w_x, t = floor(rand[j] W / 2^64) and out[j] is the first x
+ * whose cumulative weight exceeds t. The weights are exact integers, so a random word always
+ * gives the same index, whatever the summation order. The caller supplies the random words (any
+ * uniform 64-bit generator). on_device != 0: rand and out are device pointers, else host memory.
+ * QD_EINVAL if the squared norm reaches 3.999 or some |alpha|^2 is not finite (weights would not
+ * fit in 64 bits), or if the state is zero. Synchronises. */
+int qd_sample(qd_state* s, const uint64_t* rand, int64_t shots, int64_t* out, int32_t on_device);
+
+/* Per-qudit outcome distributions: out[o_q + v] = sum of p_x over the basis states whose digit q
+ * is v, o_q = d_0 + ... + d_{q-1} (host array of d_0 + ... + d_{n-1} doubles). FP64, p as in
+ * qd_sample, summed in a fixed order (repeated calls return identical values). Synchronises. */
+int qd_marginals(qd_state* s, double* out);
+
+/* The basis states that carry probability (run() output, Sec. 3.6 and Sec. 3.8): every x with
+ * p_x > eps (eps >= 0; 0 lists the states of non-zero probability), in ascending order. *count
+ * receives how many there are; the first min(count, max_out) are written to the host arrays that
+ * are not NULL: idx (basis index), amps (amplitude in the state's precision, interleaved re, im)
+ * and probs (p_x in FP64). Synchronises. */
+int qd_support(qd_state* s, double eps, int64_t max_out, int64_t* idx, void* amps, double* probs,
+               int64_t* count);
+
+/* Ket label of basis index x (Sec. 3.8 OutputType print; Sec. 3.9 prints |120> for q0 = 1, q1 = 2,
+ * q2 = 0): digits of qudit 0 first, side by side when every radix is at most 10, else separated by
+ * commas; written NUL-terminated to buf. QD_EINVAL if x is outside the register or buf is too
+ * small. Host only. */
+int qd_ket_string(const int32_t* dims, int32_t n, int64_t index, char* buf, int32_t buflen);
+
 /* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
 
 /* nc independent registers in one device arena: circuit c has n_per[c] qudits whose dims follow

@@ -31,7 +31,7 @@ __all__ = [
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
     "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_block_gates", "qd_fused_download_block",
     "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare", "qd_compare_ex",
-    "qd_normalize",
+    "qd_normalize", "qd_sample", "qd_sample_device", "qd_marginals", "qd_support", "qd_ket_string", "kets",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
     "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
     "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_tune_save", "qd_batch_autotune",
@@ -108,6 +108,10 @@ _SIGS = {
     "qd_compare": (C.c_int, [_P, _P, _DP, _DP, _DP]),
     "qd_compare_ex": (C.c_int, [_P, _P, _DP]),
     "qd_normalize": (C.c_int, [_P, _DP]),
+    "qd_sample": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32]),
+    "qd_marginals": (C.c_int, [_P, _DP]),
+    "qd_support": (C.c_int, [_P, C.c_double, C.c_int64, _P, _P, _P, _I64P]),
+    "qd_ket_string": (C.c_int, [_I32P, C.c_int32, C.c_int64, C.c_char_p, C.c_int32]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
     "qd_batch_offset": (C.c_int, [_P, C.c_int32, _I64P]),
@@ -427,6 +431,61 @@ def qd_normalize(s: int) -> float:
     v = C.c_double()
     _check(load().qd_normalize(_P(s), C.byref(v)))
     return float(v.value)
+
+
+# ------------------------------------------------------------------------------ measurement
+def qd_sample(s: int, rand) -> np.ndarray:
+    """Shot outcomes (basis indices, int64) for the uniform 64-bit random words `rand` (host)."""
+    r = np.ascontiguousarray(np.asarray(rand, dtype=np.uint64))
+    out = np.empty(r.size, dtype=np.int64)
+    _check(load().qd_sample(_P(s), r.ctypes.data_as(_P), r.size, out.ctypes.data_as(_P), 0))
+    return out
+
+
+def qd_sample_device(s: int, rand_dev_ptr: int, shots: int, out_dev_ptr: int) -> None:
+    """Shots with the random words and the outcomes in device memory."""
+    _check(load().qd_sample(_P(s), _P(rand_dev_ptr), int(shots), _P(out_dev_ptr), 1))
+
+
+def qd_marginals(s: int) -> list:
+    """Per-qudit outcome distributions (FP64): entry q has d_q values."""
+    dims = qd_state_dims(s)
+    out = np.empty(int(sum(dims)), dtype=np.float64)
+    _check(load().qd_marginals(_P(s), _dptr(out)))
+    offs = np.cumsum([0] + dims)
+    return [out[offs[q]:offs[q + 1]].copy() for q in range(len(dims))]
+
+
+def qd_support(s: int, eps: float = 0.0, max_out: Optional[int] = None):
+    """States with probability > eps, ascending: (indices, amplitudes, probabilities, count).
+    At most max_out entries are returned (all when None); count is the full number."""
+    cnt = C.c_int64()
+    _check(load().qd_support(_P(s), float(eps), 0, None, None, None, C.byref(cnt)))
+    n = cnt.value if max_out is None else min(cnt.value, int(max_out))
+    cdt = np.complex128 if qd_state_precision(s) == QD_C128 else np.complex64
+    idx = np.empty(n, dtype=np.int64)
+    amps = np.empty(n, dtype=cdt)
+    probs = np.empty(n, dtype=np.float64)
+    if n:
+        _check(load().qd_support(_P(s), float(eps), n, idx.ctypes.data_as(_P), amps.ctypes.data_as(_P),
+                                 probs.ctypes.data_as(_P), C.byref(cnt)))
+    return idx, amps, probs, int(cnt.value)
+
+
+def qd_ket_string(dims, index: int) -> str:
+    buf = C.create_string_buffer(8 * len(dims) + 8)
+    _check(load().qd_ket_string(_i32(dims), len(dims), int(index), buf, len(buf)))
+    return buf.value.decode()
+
+
+def kets(s: int, eps: float = 0.0, method: str = "probability"):
+    """run() output in the paper's print form: one {ket: value} per state with probability > eps,
+    value the probability (method "probability") or the amplitude (method "amplitude")."""
+    dims = qd_state_dims(s)
+    idx, amps, probs, _ = qd_support(s, eps)
+    vals = probs if method == "probability" else amps
+    return [{qd_ket_string(dims, int(i)): (float(v) if method == "probability" else complex(v))}
+            for i, v in zip(idx, vals)]
 
 
 # ------------------------------------------------------------------------------ batch

@@ -118,6 +118,8 @@ struct qd_state {
   qd::ParamRing ring;
   double* red = nullptr;      // reduction partials
   size_t red_cap = 0;         // in doubles
+  void* mws = nullptr;        // measurement workspace (sums of weights, marginal partials, staging)
+  size_t mws_cap = 0;         // in bytes
 };
 
 namespace qd {

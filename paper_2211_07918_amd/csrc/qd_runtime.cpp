@@ -476,6 +476,7 @@ void qd_state_free(qd_state* s) {
   (void)hipStreamSynchronize(s->stream);
   if (s->owned && s->data) (void)hipFree(s->data);
   if (s->red) (void)hipFree(s->red);
+  if (s->mws) (void)hipFree(s->mws);
   ring_free(&s->ring);
   delete s;
 }
