@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
     ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--extras", default="copy,qft,brick,batch",
+    ap.add_argument("--extras", default="copy,qft,brick,batch,measure",
                     help="comma list of extras: copy, qft, brick, batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -247,6 +247,44 @@ def bench_fused(Q, torch, circ, maxb, name, warm=True):
     return out
 
 
+def bench_measure(Q, torch, circ, shots=1_000_000, reps=3):
+    """Readout of the benchmark register after its 500 gates (complex128): shots of a measurement
+    of every qudit with the random words already in device memory, per-qudit marginals, and the
+    number of states above 1e-12. Each call synchronises; the best of `reps` wall times counts."""
+    import numpy as np
+    stream = torch.cuda.current_stream().cuda_stream
+    s = Q.qd_state_init(circ.dims, Q.QD_C128, stream)
+    for g in circ.gates:
+        Q.apply_circuit_gate(s, g, circ.dims)
+    r = np.random.default_rng(2024).integers(0, 2 ** 64, shots, dtype=np.uint64, endpoint=False)
+    rt = torch.from_numpy(r.view(np.int64)).to("cuda")
+    out = torch.empty(shots, dtype=torch.int64, device="cuda")
+
+    def best(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    t_sample = best(lambda: Q.qd_sample_device(s, rt.data_ptr(), shots, out.data_ptr()))
+    t_marg = best(lambda: Q.qd_marginals(s))
+    count = Q.qd_support(s, 1e-12, max_out=0)[3]
+    t_supp = best(lambda: Q.qd_support(s, 1e-12, max_out=0))
+    Q.qd_state_free(s)
+    state_bytes = 16.0 * circ.D
+    res = {"D": circ.D, "shots": shots,
+           "sample_ms": t_sample * 1e3, "shots_per_s": shots / t_sample,
+           "sample_state_GBps": state_bytes / t_sample / 1e9,
+           "marginals_ms": t_marg * 1e3, "marginals_state_GBps": state_bytes / t_marg / 1e9,
+           "support_count_ms": t_supp * 1e3, "support_count_state_GBps": state_bytes / t_supp / 1e9,
+           "states_above_1e-12": int(count)}
+    return res
+
+
 def bench_batch(Q, torch, ncirc=4096):
     """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
     layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
@@ -381,6 +419,11 @@ def main():
         bb = extras["batched_4096_circuits"]
         log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers, {bb['amp_upd_per_s']:.3e} amp-upd/s, "
             f"x{bb['speedup_vs_one_by_one']:.1f} vs one by one")
+    if "measure" in which:
+        mm = bench_measure(Q, torch, circ)
+        extras["measurement_hybrid20q"] = mm
+        log(f"measurement: {mm['shots']} shots in {mm['sample_ms']:.2f} ms ({mm['shots_per_s']:.3e} shots/s), "
+            f"marginals {mm['marginals_ms']:.2f} ms, support count {mm['support_count_ms']:.2f} ms")
     if tuning:
         extras["tuning"] = tuning
     out = {

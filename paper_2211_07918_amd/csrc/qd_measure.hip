@@ -84,34 +84,47 @@ __device__ __forceinline__ uint64_t wave_sum_checked(uint64_t v, bool* over) {
 
 enum { VAL_WEIGHT = 0, VAL_SUPPORT = 1 };
 
-// chunk[c] = sum over the chunk's amplitudes of their value (weight, or p > eps)
+// chunk[c] = sum over the chunk's amplitudes of their value (weight, or p > eps); a wavefront
+// takes four chunks per iteration so that four loads per lane are in flight
 template <typename R, int V>
 __global__ __launch_bounds__(256) void k_chunk_values(const R* psi_raw, uint64_t D, double eps, uint64_t* chunk,
                                                       uint32_t* flag) {
   using C = typename CxM<R>::T;
+  constexpr int U = 4;
   const C* psi = reinterpret_cast<const C*>(psi_raw);
   const uint64_t nch = (D + kChunk - 1) / kChunk;
   const uint32_t l = threadIdx.x & 63;
   const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
-  for (uint64_t c = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nch; c += nwaves) {
-    const uint64_t i = c * kChunk + l;
-    uint64_t v = 0;
-    bool bad = false;
-    if (i < D) {
-      const double p = prob_exact(ld_stream(psi + i));
-      if (V == VAL_WEIGHT) {
-        bad = !(p < kMaxProb);
-        v = weight_of(p);
-      } else {
-        v = p > eps ? 1u : 0u;
-      }
+  for (uint64_t c0 = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c0 < nch; c0 += nwaves * U) {
+    C a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = (c0 + uint64_t(u) * nwaves) * kChunk + l;
+      if (i < D) a[u] = ld_stream(psi + i);
     }
-    bool over = false;
-    const uint64_t s = wave_sum_checked(v, &over);
-    if (bad) flag[0] = 1u;
-    if (l == 0) {
-      chunk[c] = s;
-      if (over) flag[0] = 1u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t c = c0 + uint64_t(u) * nwaves;
+      if (c >= nch) break;   // wave-uniform
+      const uint64_t i = c * kChunk + l;
+      uint64_t v = 0;
+      bool bad = false;
+      if (i < D) {
+        const double p = prob_exact(a[u]);
+        if (V == VAL_WEIGHT) {
+          bad = !(p < kMaxProb);
+          v = weight_of(p);
+        } else {
+          v = p > eps ? 1u : 0u;
+        }
+      }
+      bool over = false;
+      const uint64_t sum = wave_sum_checked(v, &over);
+      if (bad) flag[0] = 1u;
+      if (l == 0) {
+        chunk[c] = sum;
+        if (over) flag[0] = 1u;
+      }
     }
   }
 }
@@ -138,11 +151,13 @@ __global__ __launch_bounds__(256) void k_block_scan(uint64_t* chunk, uint64_t nc
   }
 }
 
-// one workgroup: block totals -> exclusive block offsets (in place) and the grand total
+// one workgroup: block totals -> exclusive block offsets (in place) and the grand total.
+// Thread t owns a contiguous segment; segment sums are scanned by wavefronts, then across the 16
+// wavefronts.
 __global__ __launch_bounds__(1024) void k_top_scan(uint64_t* blk, uint64_t nb, uint64_t* total, uint32_t* flag) {
-  __shared__ uint64_t seg_sum[1024];
+  __shared__ uint64_t wtot[16];
   __shared__ uint32_t s_over;
-  const uint32_t t = threadIdx.x;
+  const uint32_t t = threadIdx.x, w = t >> 6, l = t & 63;
   const uint64_t seg = (nb + 1023) / 1024;
   const uint64_t s0 = std::min<uint64_t>(nb, uint64_t(t) * seg), s1 = std::min<uint64_t>(nb, s0 + seg);
   if (t == 0) s_over = 0;
@@ -153,14 +168,17 @@ __global__ __launch_bounds__(1024) void k_top_scan(uint64_t* blk, uint64_t nb, u
     over |= n < s;
     s = n;
   }
-  seg_sum[t] = s;
+  bool wover = false;
+  const uint64_t ws = wave_sum_checked(s, &wover);
+  const uint64_t incl = wave_inclusive_scan(s, l);
+  if (l == 0) wtot[w] = ws;
   __syncthreads();
-  if (over) s_over = 1;
+  if (over || wover) s_over = 1;
   if (t == 0) {
     uint64_t acc = 0;
-    for (int k = 0; k < 1024; ++k) {
-      const uint64_t v = seg_sum[k];
-      seg_sum[k] = acc;
+    for (int k = 0; k < 16; ++k) {
+      const uint64_t v = wtot[k];
+      wtot[k] = acc;
       const uint64_t n = acc + v;
       if (n < acc) s_over = 1;
       acc = n;
@@ -168,54 +186,89 @@ __global__ __launch_bounds__(1024) void k_top_scan(uint64_t* blk, uint64_t nb, u
     total[0] = acc;
   }
   __syncthreads();
-  uint64_t a = seg_sum[t];
+  uint64_t a = wtot[w] + (incl - s);
   for (uint64_t i = s0; i < s1; ++i) {
     const uint64_t v = blk[i];
     blk[i] = a;
     a += v;
   }
+  __syncthreads();
   if (t == 0 && s_over) flag[0] = 1u;
 }
 
+// four shots per wavefront in lockstep, so their chains of dependent loads overlap
 template <typename R>
 __global__ __launch_bounds__(256) void k_sample_shots(const R* psi_raw, uint64_t D, const uint64_t* chunkx,
                                                       uint64_t nch, const uint64_t* boff, uint64_t nb,
                                                       const uint64_t* totalp, const uint64_t* rnd, uint64_t shots,
                                                       int64_t* out) {
   using C = typename CxM<R>::T;
+  constexpr int S = 4;
   const C* psi = reinterpret_cast<const C*>(psi_raw);
   const uint32_t l = threadIdx.x & 63;
   const uint64_t W = totalp[0];
   const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
-  for (uint64_t j = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; j < shots; j += nwaves) {
-    const uint64_t t = __umul64hi(rnd[j], W);   // 0 <= t < W
-    // block: the last b with boff[b] <= t (boff[0] = 0, nondecreasing); range [lo, lo + n)
-    uint64_t lo = 0, n = nb;
-    while (n > 1) {
-      const uint64_t step = (n + 63) / 64;
-      const uint64_t off = uint64_t(l) * step;
-      const bool ok = off < n && boff[lo + off] <= t;
-      const uint64_t m = __ballot(ok);
-      const uint64_t k = uint64_t(63 - __clzll(m));   // lane 0 always holds: boff[lo] <= t
-      lo += k * step;
-      n = std::min<uint64_t>(step, n - k * step);
+  for (uint64_t j0 = ((uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * S; j0 < shots; j0 += nwaves * S) {
+    uint64_t t[S], lo[S], n[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint64_t j = j0 + k;
+      t[k] = j < shots ? __umul64hi(rnd[j], W) : 0;   // 0 <= t < W
+      lo[k] = 0;
+      n[k] = nb;
     }
-    const uint64_t b = lo;
+    // block: the last b with boff[b] <= t (boff[0] = 0, nondecreasing); range [lo, lo + n)
+    bool more = nb > 1;
+    while (more) {
+      uint64_t step[S];
+      bool ok[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        step[k] = (n[k] + 63) / 64;
+        const uint64_t off = uint64_t(l) * step[k];
+        ok[k] = n[k] > 1 && off < n[k] && boff[lo[k] + off] <= t[k];
+      }
+      more = false;
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const uint64_t m = __ballot(ok[k]);
+        if (n[k] > 1) {   // wave-uniform; lane 0 always holds: boff[lo] <= t
+          const uint64_t q = uint64_t(63 - __clzll(m));
+          lo[k] += q * step[k];
+          n[k] = std::min<uint64_t>(step[k], n[k] - q * step[k]);
+          more |= n[k] > 1;
+        }
+      }
+    }
     // chunk: the last k with chunkx[b 128 + k] <= t - boff[b]
-    const uint64_t r1 = t - boff[b];
-    const uint64_t c0 = b * kBlockChunks;
-    const bool ok0 = c0 + l < nch && chunkx[c0 + l] <= r1;
-    const bool ok1 = c0 + 64 + l < nch && chunkx[c0 + 64 + l] <= r1;
-    const uint64_t m0 = __ballot(ok0), m1 = __ballot(ok1);
-    const uint64_t kc = m1 ? uint64_t(64 + 63 - __clzll(m1)) : uint64_t(63 - __clzll(m0));
-    const uint64_t c = c0 + kc;
-    const uint64_t r2 = r1 - chunkx[c];
+    uint64_t r1[S], c0[S], a0[S], a1[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      r1[k] = t[k] - boff[lo[k]];
+      c0[k] = lo[k] * kBlockChunks;
+      a0[k] = c0[k] + l < nch ? chunkx[c0[k] + l] : ~0ull;
+      a1[k] = c0[k] + 64 + l < nch ? chunkx[c0[k] + 64 + l] : ~0ull;
+    }
+    uint64_t c[S], r2[S];
+    C amp[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint64_t m0 = __ballot(a0[k] <= r1[k]), m1 = __ballot(a1[k] <= r1[k]);
+      const uint64_t kc = m1 ? uint64_t(64 + 63 - __clzll(m1)) : uint64_t(63 - __clzll(m0));
+      c[k] = c0[k] + kc;
+      r2[k] = r1[k] - chunkx[c[k]];
+      const uint64_t i = c[k] * kChunk + l;
+      if (i < D) amp[k] = psi[i];
+    }
     // amplitude: the first lane whose inclusive weight exceeds r2
-    const uint64_t i = c * kChunk + l;
-    const uint64_t w = i < D ? weight_of(prob_exact(psi[i])) : 0;
-    const uint64_t x = wave_inclusive_scan(w, l);
-    const uint64_t m = __ballot(x > r2);
-    if (l == 0) out[j] = int64_t(c * kChunk + uint64_t(__ffsll(static_cast<long long>(m)) - 1));
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint64_t i = c[k] * kChunk + l;
+      const uint64_t w = i < D ? weight_of(prob_exact(amp[k])) : 0;
+      const uint64_t x = wave_inclusive_scan(w, l);
+      const uint64_t m = __ballot(x > r2[k]);
+      if (l == 0 && j0 + k < shots) out[j0 + k] = int64_t(c[k] * kChunk + uint64_t(__ffsll(static_cast<long long>(m)) - 1));
+    }
   }
 }
 
@@ -289,11 +342,26 @@ __global__ __launch_bounds__(256) void k_marg_rows(const In* in, uint32_t T, uin
   }
 }
 
-__global__ __launch_bounds__(256) void k_marg_cols(const double* colp, uint32_t G, uint32_t T, double* colsum) {
+// column sums over the G partials in two fixed-order stages: workgroup (x, y) takes 64 columns and
+// the partials g = y, y + 8, ... (4 wavefronts interleaved), then 8 values per column
+constexpr uint32_t kColSplit = 8;
+__global__ __launch_bounds__(256) void k_marg_cols(const double* colp, uint32_t G, uint32_t T, double* part) {
+  __shared__ double sh[4][64];
+  const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t j = blockIdx.x * 64 + l, y = blockIdx.y;
+  double s = 0.0;
+  if (j < T)
+    for (uint32_t g = y + kColSplit * w; g < G; g += kColSplit * 4) s += colp[uint64_t(g) * T + j];
+  sh[w][l] = s;
+  __syncthreads();
+  if (w == 0 && j < T) part[uint64_t(y) * T + j] = ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+}
+
+__global__ __launch_bounds__(256) void k_marg_cols_final(const double* part, uint32_t T, double* colsum) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= T) return;
   double s = 0.0;
-  for (uint32_t g = 0; g < G; ++g) s += colp[uint64_t(g) * T + j];
+  for (uint32_t y = 0; y < kColSplit; ++y) s += part[uint64_t(y) * T + j];
   colsum[j] = s;
 }
 
@@ -303,7 +371,8 @@ __global__ __launch_bounds__(256) void k_marg_rowsum(const double* rowp, uint64_
 }
 
 // marginals of the qudits that vary inside a row: pair (q, v) sums the column sums whose digit
-// (j / stride) mod dim equals v; one thread per pair, columns in ascending order
+// (j / stride) mod dim equals v, i.e. the columns a (dim stride) + v stride + b. One wavefront per
+// pair: lane l takes every 64th such column, then a fixed butterfly adds the lanes.
 struct LowQudits {
   int32_t nq;
   int32_t dim[QD_MAX_QUDITS];
@@ -313,18 +382,24 @@ struct LowQudits {
 };
 
 __global__ __launch_bounds__(256) void k_marg_low(const double* colsum, uint32_t T, LowQudits lq, double* out) {
-  const int p = int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= lq.npairs) return;
+  const int p = int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t l = threadIdx.x & 63;
+  if (p >= lq.npairs) return;   // wave-uniform
   int q = 0, v = p;
   while (v >= lq.dim[q]) {
     v -= lq.dim[q];
     ++q;
   }
   const uint32_t d = uint32_t(lq.dim[q]), st = uint32_t(lq.stride[q]);
+  const uint32_t cnt = T / d;   // columns with this digit: (T / (d st)) runs of st
   double s = 0.0;
-  for (uint32_t j = 0; j < T; ++j)
-    if ((j / st) % d == uint32_t(v)) s += colsum[j];
-  out[lq.out_off[q] + v] = s;
+  for (uint32_t e = l; e < cnt; e += 64) {
+    const uint32_t a = e / st, b = e - a * st;
+    s += colsum[a * d * st + uint32_t(v) * st + b];
+  }
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+  if (l == 0) out[lq.out_off[q] + v] = s;
 }
 
 // ------------------------------------------------------------------------------------------ host side
@@ -373,10 +448,10 @@ int scan_values(qd_state* s, int v, double eps, size_t extra, MeasureWs* w, size
   QD_HIP(hipMemsetAsync(w->flag, 0, sizeof(uint64_t), s->stream));
   const R* psi = reinterpret_cast<const R*>(s->data);
   if (v == VAL_WEIGHT)
-    hipLaunchKernelGGL((k_chunk_values<R, VAL_WEIGHT>), dim3(wave_grid(w->nch)), dim3(256), 0, s->stream, psi, D, eps,
+    hipLaunchKernelGGL((k_chunk_values<R, VAL_WEIGHT>), dim3(wave_grid((w->nch + 3) / 4)), dim3(256), 0, s->stream, psi, D, eps,
                        w->chunk, w->flag);
   else
-    hipLaunchKernelGGL((k_chunk_values<R, VAL_SUPPORT>), dim3(wave_grid(w->nch)), dim3(256), 0, s->stream, psi, D, eps,
+    hipLaunchKernelGGL((k_chunk_values<R, VAL_SUPPORT>), dim3(wave_grid((w->nch + 3) / 4)), dim3(256), 0, s->stream, psi, D, eps,
                        w->chunk, w->flag);
   QD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_block_scan, dim3(wave_grid(w->nb)), dim3(256), 0, s->stream, w->chunk, w->nch, w->blk, w->flag);
@@ -417,7 +492,7 @@ int sample_t(qd_state* s, const uint64_t* rand, int64_t shots, int64_t* out, int
     d_out = reinterpret_cast<int64_t*>(r + shots);
     QD_HIP(hipMemcpyAsync(r, rand, size_t(shots) * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream));
   }
-  hipLaunchKernelGGL((k_sample_shots<R>), dim3(wave_grid(uint64_t(shots))), dim3(256), 0, s->stream,
+  hipLaunchKernelGGL((k_sample_shots<R>), dim3(wave_grid((uint64_t(shots) + 3) / 4)), dim3(256), 0, s->stream,
                      reinterpret_cast<const R*>(s->data), uint64_t(s->reg.D), w.chunk, w.nch, w.blk, w.nb, w.total,
                      d_rand, uint64_t(shots), d_out);
   QD_HIP(hipGetLastError());
@@ -466,7 +541,7 @@ int support_t(qd_state* s, double eps, int64_t max_out, int64_t* idx, void* amps
 // one marginal level over a register (dims, n) whose entries are `in` (complex state or FP64)
 template <typename In>
 int marg_level(qd_state* s, const In* in, const int32_t* dims, int n, int32_t out_first, double* out_dev,
-               double* colp, double* rowp, double* colsum, double* rows_a, double* rows_b) {
+               double* colp, double* rowp, double* colsum, double* colpart, double* rows_a, double* rows_b) {
   int64_t st[QD_MAX_QUDITS];
   int64_t acc = 1;
   for (int q = n - 1; q >= 0; --q) {
@@ -483,7 +558,9 @@ int marg_level(qd_state* s, const In* in, const int32_t* dims, int n, int32_t ou
   const uint32_t G = uint32_t(std::min<uint64_t>(R, kMargGrid));
   hipLaunchKernelGGL((k_marg_rows<In>), dim3(G), dim3(256), 0, s->stream, in, T, R, colp, rowp);
   QD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_marg_cols, dim3((T + 255) / 256), dim3(256), 0, s->stream, colp, G, T, colsum);
+  hipLaunchKernelGGL(k_marg_cols, dim3((T + 63) / 64, kColSplit), dim3(256), 0, s->stream, colp, G, T, colpart);
+  QD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_marg_cols_final, dim3((T + 255) / 256), dim3(256), 0, s->stream, colpart, T, colsum);
   QD_HIP(hipGetLastError());
   LowQudits lq{};
   lq.nq = n - k_low;
@@ -498,13 +575,13 @@ int marg_level(qd_state* s, const In* in, const int32_t* dims, int n, int32_t ou
     pairs += dims[q];
   }
   lq.npairs = pairs;
-  hipLaunchKernelGGL(k_marg_low, dim3((pairs + 255) / 256), dim3(256), 0, s->stream, colsum, T, lq, out_dev);
+  hipLaunchKernelGGL(k_marg_low, dim3((pairs + 3) / 4), dim3(256), 0, s->stream, colsum, T, lq, out_dev);
   QD_HIP(hipGetLastError());
   if (k_low == 0) return QD_OK;
   hipLaunchKernelGGL(k_marg_rowsum, dim3(unsigned((R + 255) / 256)), dim3(256), 0, s->stream, rowp, R, rows_a);
   QD_HIP(hipGetLastError());
   // the row totals are a probability vector over qudits 0..k_low-1
-  return marg_level<double>(s, rows_a, dims, k_low, out_first, out_dev, colp, rowp, colsum, rows_b, rows_a);
+  return marg_level<double>(s, rows_a, dims, k_low, out_first, out_dev, colp, rowp, colsum, colpart, rows_b, rows_a);
 }
 
 template <typename R>
@@ -518,18 +595,19 @@ int marginals_t(qd_state* s, double* out) {
   while (k > 0 && uint64_t(r.strides[k - 1]) * uint64_t(r.dims[k - 1]) <= kMargRow) --k;
   const uint64_t R0 = uint64_t(r.D) / (uint64_t(r.strides[k]) * uint64_t(r.dims[k]));
   const size_t ncolp = size_t(kMargGrid) * kMargRow;
-  const size_t doubles = ncolp + 4 * R0 + kMargRow + 2 * R0 + size_t(nout);
+  const size_t doubles = ncolp + 4 * R0 + kMargRow * (1 + kColSplit) + 2 * R0 + size_t(nout);
   int rc = ensure_ws(s, doubles * sizeof(double));
   if (rc) return rc;
   double* colp = reinterpret_cast<double*>(s->mws);
   double* rowp = colp + ncolp;
   double* colsum = rowp + 4 * R0;
-  double* rows_a = colsum + kMargRow;
+  double* colpart = colsum + kMargRow;
+  double* rows_a = colpart + size_t(kColSplit) * kMargRow;
   double* rows_b = rows_a + R0;
   double* out_dev = rows_b + R0;
   using C = typename CxM<R>::T;
-  rc = marg_level<C>(s, reinterpret_cast<const C*>(s->data), r.dims, r.n, 0, out_dev, colp, rowp, colsum, rows_a,
-                     rows_b);
+  rc = marg_level<C>(s, reinterpret_cast<const C*>(s->data), r.dims, r.n, 0, out_dev, colp, rowp, colsum, colpart,
+                     rows_a, rows_b);
   if (rc) return rc;
   QD_HIP(hipMemcpyAsync(out, out_dev, size_t(nout) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   QD_HIP(hipStreamSynchronize(s->stream));
