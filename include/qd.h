@@ -330,13 +330,16 @@ void qd_batch_free(qd_batch* b);
 /* ---------------------------------------------------------------- tuning and calibration */
 
 /* Tile parameters the launchers use (QD_TUNE_* below): threads per workgroup (64, 128, 192 or
- * 256), slices per thread (1, 2 or 4), amplitudes per LDS tile (power of two, 256..4096),
- * slice columns per fused tile (32, 64, 128) and the target stride below which a gate is staged
- * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes). 0 restores the default. Process-wide, host only;
- * QD_EINVAL for an unknown parameter or a value outside its range. */
+ * 256), slices per thread (1, 2 or 4; the batched kernel also 8), amplitudes per LDS tile (power of two, 256..4096),
+ * slice columns per fused tile (32, 64, 128), the target stride below which a gate is staged
+ * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes) and the workgroups per compute unit of the batched
+ * layer kernel (QD_TUNE_BATCH_GRID: 1..63 persistent workgroups walk the tile list; 64 launches one
+ * workgroup per tile). 0 restores the default. Process-wide,
+ * host only; QD_EINVAL for an unknown parameter or a value outside its range. */
 enum { QD_TUNE_DIRECT_BLOCK = 0, QD_TUNE_DIRECT_SPT = 1, QD_TUNE_TILE_BLOCK = 2,
        QD_TUNE_TILE_ELEMS = 3, QD_TUNE_DIAG_BLOCK = 4, QD_TUNE_BATCH_BLOCK = 5,
-       QD_TUNE_BATCH_SPT = 6, QD_TUNE_FUSED_COLS = 7, QD_TUNE_RUN_MIN = 8, QD_TUNE_COUNT = 9 };
+       QD_TUNE_BATCH_SPT = 6, QD_TUNE_FUSED_COLS = 7, QD_TUNE_RUN_MIN = 8, QD_TUNE_BATCH_GRID = 9,
+       QD_TUNE_COUNT = 10 };
 int qd_tune_set(int32_t param, int32_t value);
 int qd_tune_get(int32_t param, int32_t* value);
 

@@ -64,31 +64,53 @@ __device__ __forceinline__ int64_t bd_offset(const BatchDesc& d, uint32_t idx) {
   return off;
 }
 
+// a thread takes the slices j0 + tid + k blockDim (k < spt <= 8) of the tile, in batches of
+// at most 16 / DT slices whose loads are all issued before the first store (the register peak of
+// the kernel stays that of about 16 amplitudes whatever the gate's dimension)
+constexpr int kBatchMaxSpt = 8;
+
+#ifndef QD_BATCH_LD
+#define QD_BATCH_LD(p) (*(p))
+#define QD_BATCH_ST(p, v) (*(p) = (v))
+#endif
+
 template <typename R, int DT>
 __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDesc& d, uint32_t j0, uint32_t j1) {
   using C = typename CxB<R>::T;
+  constexpr int KB = (16 / DT) < 1 ? 1 : ((16 / DT) > kBatchMaxSpt ? kBatchMaxSpt : (16 / DT));
   C* psi = reinterpret_cast<C*>(a.arena) + d.off;
   const R* U = a.upool + d.uoff;
-  for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    const int64_t b = bd_offset(d, j);
-    C x[DT];
+  for (int k0 = 0; k0 < int(a.spt); k0 += KB) {
+    int64_t b[KB];
+    C x[KB][DT];
 #pragma unroll
-    for (int y = 0; y < DT; ++y) x[y] = psi[b + y * d.st];
+    for (int k = 0; k < KB; ++k) {
+      const uint32_t j = j0 + threadIdx.x + uint32_t(k0 + k) * blockDim.x;
+      b[k] = (k0 + k < int(a.spt) && j < j1) ? bd_offset(d, j) : -1;
+      if (b[k] >= 0) {
 #pragma unroll
-    for (int r = 0; r < DT; ++r) {
-      R re = R(0), im = R(0);
-#pragma unroll
-      for (int c = 0; c < DT; ++c) {
-        const R ur = U[2 * (r * DT + c)], ui = U[2 * (r * DT + c) + 1];
-        re = fma(ur, x[c].x, re);
-        re = fma(-ui, x[c].y, re);
-        im = fma(ur, x[c].y, im);
-        im = fma(ui, x[c].x, im);
+        for (int y = 0; y < DT; ++y) x[k][y] = QD_BATCH_LD(psi + (b[k] + y * d.st));
       }
-      C yv;
-      yv.x = re;
-      yv.y = im;
-      psi[b + r * d.st] = yv;
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      if (b[k] < 0) continue;
+#pragma unroll
+      for (int r = 0; r < DT; ++r) {
+        R re = R(0), im = R(0);
+#pragma unroll
+        for (int c = 0; c < DT; ++c) {
+          const R ur = U[2 * (r * DT + c)], ui = U[2 * (r * DT + c) + 1];
+          re = fma(ur, x[k][c].x, re);
+          re = fma(-ui, x[k][c].y, re);
+          im = fma(ur, x[k][c].y, im);
+          im = fma(ui, x[k][c].x, im);
+        }
+        C yv;
+        yv.x = re;
+        yv.y = im;
+        QD_BATCH_ST(psi + (b[k] + r * d.st), yv);
+      }
     }
   }
 }
@@ -274,7 +296,10 @@ static int apply_layer_t(qd_batch* b, const qd_gate* gates) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const unsigned grid = std::max(1u, std::min<unsigned>(ntiles, unsigned(cus) * 8));
+  // batch_wpc persistent workgroups per compute unit walk the tile list; 64 = one workgroup per tile
+  const int wpc = tune().batch_wpc;
+  const unsigned grid = wpc >= 64 ? std::max(1u, ntiles)
+                                  : std::max(1u, std::min<unsigned>(ntiles, unsigned(cus) * unsigned(wpc)));
   BatchArgs<R> a;
   a.arena = reinterpret_cast<R*>(b->arena);
   a.ncirc = uint32_t(desc.size());
@@ -424,17 +449,19 @@ int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
   QD_HIP(hipMalloc(&save, bytes));
   hipError_t e = hipMemcpyAsync(save, b->arena, bytes, hipMemcpyDeviceToDevice, b->stream);
   TuneParams& tp = tune();
-  const int old_block = tp.batch_block, old_spt = tp.batch_spt;
-  int best_block = old_block, best_spt = old_spt, rc = QD_OK;
+  const int old_block = tp.batch_block, old_spt = tp.batch_spt, old_wpc = tp.batch_wpc;
+  int best_block = old_block, best_spt = old_spt, best_wpc = old_wpc, rc = QD_OK;
   float best = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   for (int blk : {128, 256})
-    for (int spt : {1, 2, 4}) {
+    for (int spt : {2, 4, 8})
+      for (int wpc : {8, 32, 64}) {
       if (e != hipSuccess || rc) break;
       tp.batch_block = blk;
       tp.batch_spt = spt;
+      tp.batch_wpc = wpc;
       rc = qd_batch_apply_layer(b, gates);  // warm-up
       if (!rc) e = hipEventRecord(e0, b->stream);
       for (int i = 0; i < 3 && !rc && e == hipSuccess; ++i) rc = qd_batch_apply_layer(b, gates);
@@ -446,10 +473,12 @@ int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
         best = ms;
         best_block = blk;
         best_spt = spt;
+        best_wpc = wpc;
       }
     }
   tp.batch_block = (rc || e != hipSuccess) ? old_block : best_block;
   tp.batch_spt = (rc || e != hipSuccess) ? old_spt : best_spt;
+  tp.batch_wpc = (rc || e != hipSuccess) ? old_wpc : best_wpc;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   hipError_t e2 = hipMemcpyAsync(b->arena, save, bytes, hipMemcpyDeviceToDevice, b->stream);

@@ -49,7 +49,8 @@ struct TuneParams {
   int tile_elems = 2048;    // amplitudes per LDS tile (complex128; doubled for complex64)
   int diag_block = 256;
   int batch_block = 256;
-  int batch_spt = 2;
+  int batch_spt = 4;
+  int batch_wpc = 64;       // batched layer kernel: 1..63 persistent workgroups per CU, 64 one per tile
   int fused_cols = 64;      // slice columns per fused-block tile
   int run_min = 16;         // a target stride below this routes the gate to the LDS tile kernel
 };

@@ -573,10 +573,13 @@ int qd_tune_set(int32_t param, int32_t value) {
       if (param == QD_TUNE_BATCH_BLOCK) t.batch_block = blk(value, def.batch_block);
       return QD_OK;
     case QD_TUNE_DIRECT_SPT:
-    case QD_TUNE_BATCH_SPT:
       if (value != 0 && value != 1 && value != 2 && value != 4) return fail(QD_EINVAL, "slices per thread must be 1, 2 or 4");
-      if (param == QD_TUNE_DIRECT_SPT) t.direct_spt = blk(value, def.direct_spt);
-      else t.batch_spt = blk(value, def.batch_spt);
+      t.direct_spt = blk(value, def.direct_spt);
+      return QD_OK;
+    case QD_TUNE_BATCH_SPT:
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(QD_EINVAL, "batch slices per thread must be 1, 2, 4 or 8");
+      t.batch_spt = blk(value, def.batch_spt);
       return QD_OK;
     case QD_TUNE_TILE_ELEMS:
       if (value != 0 && (value < 256 || value > 4096 || (value & (value - 1)))) return fail(QD_EINVAL, "tile must be a power of two in 256..4096");
@@ -589,6 +592,10 @@ int qd_tune_set(int32_t param, int32_t value) {
     case QD_TUNE_RUN_MIN:
       if (value > 1024) return fail(QD_EINVAL, "run threshold must be 1..1024");
       t.run_min = blk(value, def.run_min);
+      return QD_OK;
+    case QD_TUNE_BATCH_GRID:
+      if (value > 64) return fail(QD_EINVAL, "workgroups per compute unit must be 1..64");
+      t.batch_wpc = blk(value, def.batch_wpc);
       return QD_OK;
     default:
       return fail(QD_EINVAL, "unknown tuning parameter");
@@ -608,6 +615,7 @@ int qd_tune_get(int32_t param, int32_t* value) {
     case QD_TUNE_BATCH_SPT: *value = t.batch_spt; return QD_OK;
     case QD_TUNE_FUSED_COLS: *value = t.fused_cols; return QD_OK;
     case QD_TUNE_RUN_MIN: *value = t.run_min; return QD_OK;
+    case QD_TUNE_BATCH_GRID: *value = t.batch_wpc; return QD_OK;
     default: return fail(QD_EINVAL, "unknown tuning parameter");
   }
 }

@@ -64,11 +64,14 @@ def test_small_batch_vs_oracle(stream, prec):
         Q.qd_batch_free(b)
 
 
-@pytest.mark.parametrize("block,spt", [(64, 1), (128, 2), (256, 4)])
-def test_batch_tile_shapes(stream, block, spt):
+@pytest.mark.parametrize("block,spt,grid", [(64, 1, 8), (128, 2, 64), (256, 4, 1), (256, 8, 64), (192, 8, 16)])
+def test_batch_tile_shapes(stream, block, spt, grid):
+    """Every tile shape and both grid modes (persistent workgroups walking the tile list, or one
+    workgroup per tile) give the oracle's states."""
     circs = small_batch(24, 12, seed=78)
     Q.qd_tune_set(Q.QD_TUNE_BATCH_BLOCK, block)
     Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT, spt)
+    Q.qd_tune_set(Q.QD_TUNE_BATCH_GRID, grid)
     b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C128, stream)
     try:
         for ga in layers_of(circs):
@@ -78,6 +81,7 @@ def test_batch_tile_shapes(stream, block, spt):
         Q.qd_batch_free(b)
         Q.qd_tune_set(Q.QD_TUNE_BATCH_BLOCK, 0)
         Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT, 0)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_GRID, 0)
     offs = np.cumsum([0] + [c.D for c in circs])
     for i, c in enumerate(circs):
         assert max_abs(arena[offs[i]:offs[i + 1]], O.run_circuit(c)) <= 1e-12

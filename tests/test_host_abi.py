@@ -144,13 +144,15 @@ def test_routes():
 
 
 def test_tune_parameters():
-    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 128), (Q.QD_TUNE_DIRECT_SPT, 1), (Q.QD_TUNE_TILE_ELEMS, 1024)):
+    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 128), (Q.QD_TUNE_DIRECT_SPT, 1), (Q.QD_TUNE_TILE_ELEMS, 1024),
+                 (Q.QD_TUNE_BATCH_GRID, 16)):
         old = Q.qd_tune_get(p)
         Q.qd_tune_set(p, v)
         assert Q.qd_tune_get(p) == v
         Q.qd_tune_set(p, 0)
         assert Q.qd_tune_get(p) == old
-    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 100), (Q.QD_TUNE_DIRECT_SPT, 3), (Q.QD_TUNE_TILE_ELEMS, 1000), (42, 1)):
+    for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 100), (Q.QD_TUNE_DIRECT_SPT, 3), (Q.QD_TUNE_TILE_ELEMS, 1000),
+                 (Q.QD_TUNE_BATCH_GRID, 65), (42, 1)):
         with pytest.raises(Q.QDError):
             Q.qd_tune_set(p, v)
 
