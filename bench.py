@@ -301,6 +301,7 @@ def bench_batch(Q, torch, ncirc=4096):
     b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C64, stream)
     Q.qd_batch_autotune(b, gas[0])
     block, spt = Q.qd_tune_get(Q.QD_TUNE_BATCH_BLOCK), Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT)
+    grid = Q.qd_tune_get(Q.QD_TUNE_BATCH_GRID)
     Q.qd_batch_capture(b, True)
     for ga in gas:
         Q.qd_batch_apply_layer(b, ga)
@@ -331,7 +332,8 @@ def bench_batch(Q, torch, ncirc=4096):
     return {"circuits": ncirc, "layers": L, "sum_D": int(sum(c.D for c in circs)), "graph_ms": ms,
             "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
             "hbm_GBps": 16.0 * upd / (ms * 1e-3) / 1e9, "one_by_one_s": one_s,
-            "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt}
+            "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt,
+            "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU"}
 
 
 def host_info():

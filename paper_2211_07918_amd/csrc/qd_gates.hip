@@ -332,26 +332,6 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
   }
 }
 
-// ------------------------------------------------------------------------------------------ utility kernels
-template <typename R>
-__global__ __launch_bounds__(256) void k_fill_basis(R* psi_raw, uint64_t D, uint64_t idx) {
-  using C = typename CxT<R>::T;
-  C* psi = reinterpret_cast<C*>(psi_raw);
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
-    C v;
-    v.x = i == idx ? R(1) : R(0);
-    v.y = R(0);
-    psi[i] = v;
-  }
-}
-
-// HBM copy ceiling: one streaming 16-byte load and store per thread (the fastest copy form
-// measured on gfx950, ahead of grid-stride loops and of several accesses per thread)
-__global__ __launch_bounds__(256) void k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n16) {
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n16) st_stream(dst + i, ld_stream(src + i));
-}
-
 // ------------------------------------------------------------------------------------------ launch helpers
 static inline unsigned grid_for(uint64_t items, uint64_t per_block) {
   const uint64_t g = (items + per_block - 1) / per_block;
@@ -648,29 +628,6 @@ static int launch_gate_t(qd_state* s, const GatePlan& p) {
 
 int launch_gate(qd_state* s, const GatePlan& p) {
   return s->prec == QD_C128 ? launch_gate_t<double>(s, p) : launch_gate_t<float>(s, p);
-}
-
-int launch_fill_basis(qd_state* s, int64_t index) {
-  const uint64_t D = uint64_t(s->reg.D);
-  const unsigned grid = unsigned(std::min<uint64_t>((D + 255) / 256, 65536));
-  if (s->prec == QD_C128)
-    hipLaunchKernelGGL((k_fill_basis<double>), dim3(grid), dim3(256), 0, s->stream, reinterpret_cast<double*>(s->data), D, uint64_t(index));
-  else
-    hipLaunchKernelGGL((k_fill_basis<float>), dim3(grid), dim3(256), 0, s->stream, reinterpret_cast<float*>(s->data), D, uint64_t(index));
-  return check_launch("k_fill_basis");
-}
-
-int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
-  const uint64_t n16 = uint64_t(bytes) / 16;
-  constexpr uint64_t kChunk = uint64_t(1) << 30;   // 16-byte units per launch (one per thread)
-  for (uint64_t o = 0; o < n16; o += kChunk) {
-    const uint64_t n = std::min(kChunk, n16 - o);
-    hipLaunchKernelGGL(k_stream_copy, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<uint4*>(dst) + o, reinterpret_cast<const uint4*>(src) + o, n);
-    const int rc = check_launch("k_stream_copy");
-    if (rc) return rc;
-  }
-  return QD_OK;
 }
 
 }  // namespace qd
