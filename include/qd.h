@@ -288,6 +288,62 @@ int qd_support(qd_state* s, double eps, int64_t max_out, int64_t* idx, void* amp
  * small. Host only. */
 int qd_ket_string(const int32_t* dims, int32_t n, int64_t index, char* buf, int32_t buflen);
 
+/* ---------------------------------------------------------------- circuit front-end (Sec. 3.4, 3.5, 4) */
+
+/* A circuit: a register and an ordered list of named gates (QD_GATE_X with shift a, QD_GATE_Z,
+ * QD_GATE_F) on one target, each with zero or more controls and their values. Host only. */
+typedef struct qd_circuit qd_circuit;
+
+/* Empty circuit on dims[0..n-1]; its qudits are named q0, q1, ... QD_EINVAL / QD_EDIM as for a
+ * register. */
+int qd_circuit_create(const int32_t* dims, int32_t n, qd_circuit** out);
+
+/* Append a gate. QD_EINVAL for an unknown kind, a target or control outside the register, a repeated
+ * qudit, a control value outside 0..d-1 or an X shift outside 1..d-1 (the circuit is unchanged). */
+int qd_circuit_add(qd_circuit* c, int32_t kind, int32_t target, int32_t a, const int32_t* controls,
+                   const int32_t* control_values, int32_t m);
+
+/* Parse a QuDiet QASM program (Sec. 4): ".qudit n", one "qudit NAME (d)" line per qudit, then the
+ * gates between ".begin" and ".end": "X q [a]" (shift a, default 1), "H q", "Z q", "CX c t [a]"
+ * and the extension "MCT c1 .. ck t [a]"; every control fires on d_c - 1 (Sec. 2.1). Names are
+ * case-insensitive, '#' starts a comment. QD_EINVAL with the line number in qd_last_error() for
+ * any malformed line, an unknown qudit or gate, a shift outside 1..d-1, a repeated qudit in one
+ * gate, a count that differs from ".qudit", or a missing ".begin"/".end". */
+int qd_qasm_parse(const char* text, qd_circuit** out);
+
+/* Number of qudits and gates; either pointer may be NULL. */
+int qd_circuit_size(const qd_circuit* c, int32_t* n_qudits, int64_t* n_gates);
+
+/* The register (n values) and the name of qudit q (NUL-terminated, lowercase). */
+int qd_circuit_dims(const qd_circuit* c, int32_t* dims_out);
+int qd_circuit_name(const qd_circuit* c, int32_t q, char* buf, int32_t buflen);
+
+/* Gate i: kind, target, shift (0 unless X), number of controls m, and the m controls and values
+ * (arrays of at least m entries, or NULL). */
+int qd_circuit_gate(const qd_circuit* c, int64_t i, int32_t* kind, int32_t* target, int32_t* a, int32_t* m,
+                    int32_t* controls, int32_t* control_values);
+
+/* Moment of every gate (Sec. 3.5): a gate moves back through the preceding Moments while all of
+ * its qudits (target and controls) hold identities there, so its Moment is one past the latest
+ * Moment of the earlier gates sharing a qudit (0-based). moment_out holds one int32 per gate (or
+ * NULL); *depth (or NULL) receives the number of Moments. Gates of one Moment touch disjoint
+ * qudits and commute. */
+int qd_circuit_moments(const qd_circuit* c, int32_t* moment_out, int32_t* depth);
+
+/* New circuit with every X of two or more controls replaced by generalized CNOTs (Sec. 3.4): for
+ * controls c_1..c_k with values v_1..v_k, c_{i-1} at its marker raises c_i by 1 (i = 2..k; the
+ * marker of c_1 is v_1, of c_i is v_i + 1), c_k at its marker shifts the target, then the chain is
+ * undone in reverse with shifts d_{c_i} - 1. Exact on every basis state whose chained controls
+ * c_2..c_k are not already at their markers (the intermediate level is free). QD_EDIM if some
+ * chained control has no level v_i + 1. Other gates are copied. */
+int qd_circuit_decompose(const qd_circuit* c, qd_circuit** out);
+
+/* Apply the circuit's gates in order to a state of the same register (qd_apply_gate for each).
+ * QD_EDIM if the registers differ. Asynchronous, like qd_apply_gate. */
+int qd_circuit_apply(qd_state* s, const qd_circuit* c);
+
+void qd_circuit_free(qd_circuit* c);
+
 /* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
 
 /* nc independent registers in one device arena: circuit c has n_per[c] qudits whose dims follow

@@ -17,9 +17,11 @@ What the paper fixes:
     cx((0,1), +2) on wires whose middle one has an extra level.
 
 Readings:
-  * names are case-insensitive; '#' starts a comment. The paper's listing has "X X2 2" (taken as
-    x2) and "CX x1 x1 2", taken as "CX x1 x2 2" as its text describes. An "MCT c1 .. ck t [a]"
-    line (extension) is a multi-controlled X whose controls fire on d_c - 1;
+  * names are case-insensitive and '#' starts a comment: the paper's sample program writes one
+    qudit's name with a capital letter, and one of its generalized CNOTs names the same qudit as
+    control and target where the text describes the second qutrit acting on the third (such a line
+    is rejected here). An "MCT c1 .. ck t [a]" line (extension) is a multi-controlled X whose
+    controls fire on d_c - 1;
   * a multi-controlled X with controls c_1..c_k (values v_1..v_k) is decomposed as a chain:
     control c_{i-1} raises c_i by 1 (i = 2..k), so c_i reaches v_i + 1 exactly when c_1..c_i all
     hold their values; the last marker shifts the target; the chain is undone in reverse order
@@ -80,9 +82,12 @@ def parse_qasm(text: str):
             continue
         args = tok[1:]
         shift = None
-        if args and args[-1].lstrip("-").isdigit():
-            shift = int(args[-1])
-            args = args[:-1]
+        if args:
+            last = args[-1]
+            body = last[1:] if last.startswith("-") else last
+            if body.isascii() and body.isdigit() and len(body) <= 6:
+                shift = int(last)
+                args = args[:-1]
         try:
             wires = [names.index(a.lower()) for a in args]
         except ValueError:

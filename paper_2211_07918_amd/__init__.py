@@ -33,6 +33,9 @@ __all__ = [
     "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_block_gates", "qd_fused_download_block",
     "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare", "qd_compare_ex",
     "qd_normalize", "qd_sample", "qd_sample_device", "qd_marginals", "qd_support", "qd_ket_string", "kets",
+    "qd_circuit_create", "qd_circuit_add", "qd_qasm_parse", "qd_circuit_size", "qd_circuit_dims", "qd_circuit_name",
+    "qd_circuit_gate", "qd_circuit_gates", "qd_circuit_moments", "qd_circuit_decompose", "qd_circuit_apply",
+    "qd_circuit_free",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
     "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
     "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_tune_save", "qd_batch_autotune",
@@ -113,6 +116,17 @@ _SIGS = {
     "qd_marginals": (C.c_int, [_P, _DP]),
     "qd_support": (C.c_int, [_P, C.c_double, C.c_int64, _P, _P, _P, _I64P]),
     "qd_ket_string": (C.c_int, [_I32P, C.c_int32, C.c_int64, C.c_char_p, C.c_int32]),
+    "qd_circuit_create": (C.c_int, [_I32P, C.c_int32, C.POINTER(_P)]),
+    "qd_circuit_add": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _I32P, _I32P, C.c_int32]),
+    "qd_qasm_parse": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
+    "qd_circuit_size": (C.c_int, [_P, _I32P, _I64P]),
+    "qd_circuit_dims": (C.c_int, [_P, _I32P]),
+    "qd_circuit_name": (C.c_int, [_P, C.c_int32, C.c_char_p, C.c_int32]),
+    "qd_circuit_gate": (C.c_int, [_P, C.c_int64, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P]),
+    "qd_circuit_moments": (C.c_int, [_P, _I32P, _I32P]),
+    "qd_circuit_decompose": (C.c_int, [_P, C.POINTER(_P)]),
+    "qd_circuit_apply": (C.c_int, [_P, _P]),
+    "qd_circuit_free": (None, [_P]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
     "qd_batch_offset": (C.c_int, [_P, C.c_int32, _I64P]),
@@ -487,6 +501,77 @@ def kets(s: int, eps: float = 0.0, method: str = "probability"):
     vals = probs if method == "probability" else amps
     return [{qd_ket_string(dims, int(i)): (float(v) if method == "probability" else complex(v))}
             for i, v in zip(idx, vals)]
+
+
+# ------------------------------------------------------------------------------ circuit front-end
+def qd_circuit_create(dims) -> int:
+    out = _P()
+    _check(load().qd_circuit_create(_i32(dims), len(dims), C.byref(out)))
+    return out.value
+
+
+def qd_circuit_add(c: int, kind: int, target: int, a: int = 0, controls=(), values=()) -> None:
+    _check(load().qd_circuit_add(_P(c), int(kind), int(target), int(a), _i32(controls), _i32(values), len(controls)))
+
+
+def qd_qasm_parse(text: str) -> int:
+    out = _P()
+    _check(load().qd_qasm_parse(text.encode(), C.byref(out)))
+    return out.value
+
+
+def qd_circuit_size(c: int):
+    n, g = C.c_int32(), C.c_int64()
+    _check(load().qd_circuit_size(_P(c), C.byref(n), C.byref(g)))
+    return int(n.value), int(g.value)
+
+
+def qd_circuit_dims(c: int) -> list:
+    n, _ = qd_circuit_size(c)
+    out = (C.c_int32 * n)()
+    _check(load().qd_circuit_dims(_P(c), out))
+    return [int(x) for x in out]
+
+
+def qd_circuit_name(c: int, q: int) -> str:
+    buf = C.create_string_buffer(256)
+    _check(load().qd_circuit_name(_P(c), int(q), buf, len(buf)))
+    return buf.value.decode()
+
+
+def qd_circuit_gate(c: int, i: int):
+    """(kind, target, a, controls, control_values) of gate i."""
+    kind, t, a, m = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    ctl, val = (C.c_int32 * 64)(), (C.c_int32 * 64)()
+    _check(load().qd_circuit_gate(_P(c), int(i), C.byref(kind), C.byref(t), C.byref(a), C.byref(m), ctl, val))
+    return int(kind.value), int(t.value), int(a.value), tuple(ctl[:m.value]), tuple(val[:m.value])
+
+
+def qd_circuit_gates(c: int) -> list:
+    return [qd_circuit_gate(c, i) for i in range(qd_circuit_size(c)[1])]
+
+
+def qd_circuit_moments(c: int):
+    """(moment of every gate, depth)."""
+    _, g = qd_circuit_size(c)
+    out = (C.c_int32 * max(1, g))()
+    depth = C.c_int32()
+    _check(load().qd_circuit_moments(_P(c), out, C.byref(depth)))
+    return [int(x) for x in out[:g]], int(depth.value)
+
+
+def qd_circuit_decompose(c: int) -> int:
+    out = _P()
+    _check(load().qd_circuit_decompose(_P(c), C.byref(out)))
+    return out.value
+
+
+def qd_circuit_apply(s: int, c: int) -> None:
+    _check(load().qd_circuit_apply(_P(s), _P(c)))
+
+
+def qd_circuit_free(c: int) -> None:
+    load().qd_circuit_free(_P(c))
 
 
 # ------------------------------------------------------------------------------ batch

@@ -51,7 +51,7 @@ def test_program_parses_and_gives_the_hand_derived_state():
     assert np.array_equal(psi, want)
 
 
-@pytest.mark.parametrize("bad", [
+MALFORMED = [
     ".qudit 2\nqudit a (2)\n.begin\n.end",                  # count mismatch
     "qudit a (2)\nqudit a (3)\n.begin\n.end",                # duplicate name
     "qudit a (1)\n.begin\n.end",                            # dimension
@@ -62,7 +62,10 @@ def test_program_parses_and_gives_the_hand_derived_state():
     "qudit a (2)\n.begin\nX a\n",                           # no .end
     "qudit a (2)\n.begin\nH a 1\n.end",                     # H takes no shift
     "qudit a (2)\n.begin\n.end\nX a",                       # after .end
-])
+]
+
+
+@pytest.mark.parametrize("bad", MALFORMED)
 def test_malformed_programs_are_rejected(bad):
     with pytest.raises(F.QasmError):
         F.parse_qasm(bad)
