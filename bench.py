@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
     ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--extras", default="copy,qft,brick,batch,measure",
+    ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend",
                     help="comma list of extras: copy, qft, brick, batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -285,6 +285,45 @@ def bench_measure(Q, torch, circ, shots=1_000_000, reps=3):
     return res
 
 
+def bench_frontend(Q, n_q=20, n_g=200_000, seed=7):
+    """Host-side front-end on a seeded program of n_g gates (H, X with shifts, Z, CX) over a
+    20-qudit hybrid register: QASM parse and Moment packing, best of three."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    dims = [int(x) for x in rng.choice([2, 3, 4], size=n_q)]
+    lines = [f".qudit {n_q}"] + [f"qudit w{i} ({d})" for i, d in enumerate(dims)] + [".begin"]
+    for _ in range(n_g):
+        t = int(rng.integers(n_q))
+        r = rng.random()
+        if r < 0.4:
+            lines.append(f"H w{t}")
+        elif r < 0.6:
+            lines.append(f"X w{t} {int(rng.integers(1, dims[t]))}")
+        elif r < 0.7:
+            lines.append(f"Z w{t}")
+        else:
+            c = int(rng.choice([q for q in range(n_q) if q != t]))
+            lines.append(f"CX w{c} w{t}")
+    lines.append(".end")
+    text = "\n".join(lines)
+
+    def best(fn):
+        t = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    t_parse = best(lambda: Q.qd_circuit_free(Q.qd_qasm_parse(text)))
+    c = Q.qd_qasm_parse(text)
+    t_mom = best(lambda: Q.qd_circuit_moments(c))
+    depth = Q.qd_circuit_moments(c)[1]
+    Q.qd_circuit_free(c)
+    return {"gates": n_g, "bytes": len(text), "parse_ms": t_parse * 1e3, "parse_gates_per_s": n_g / t_parse,
+            "moments_ms_incl_binding": t_mom * 1e3, "depth": depth}
+
+
 def bench_batch(Q, torch, ncirc=4096):
     """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
     layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
@@ -421,6 +460,10 @@ def main():
         bb = extras["batched_4096_circuits"]
         log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers, {bb['amp_upd_per_s']:.3e} amp-upd/s, "
             f"x{bb['speedup_vs_one_by_one']:.1f} vs one by one")
+    if "frontend" in which:
+        fe = bench_frontend(Q)
+        extras["frontend_qasm"] = fe
+        log(f"front-end: {fe['gates']} QASM gates parsed in {fe['parse_ms']:.1f} ms, depth {fe['depth']}")
     if "measure" in which:
         mm = bench_measure(Q, torch, circ)
         extras["measurement_hybrid20q"] = mm
