@@ -12,8 +12,9 @@ Readings (each shared with the library and stated in its header):
   * an index is present exactly when its amplitude is not exactly zero: a gate output whose real
     and imaginary parts are both exactly 0.0 is dropped (sparse matrix products store no exact
     zeros). Entries moved by a monomial gate are never dropped;
-  * a gate is *monomial* when every column of U holds exactly one entry that is not exactly zero
-    (shifts, generalized CNOTs, Z_d, controlled phases, qudit swaps); it maps each matching entry
+  * a gate is *monomial* when every column and every row of U holds exactly one entry that is not
+    exactly zero (shifts, generalized CNOTs, Z_d, controlled phases, qudit swaps), so that distinct
+    indices stay distinct; it maps each matching entry
     to one entry: column loc goes to the row r holding that column's entry and the amplitude is
     multiplied by U[r, loc], except that a multiplier of exactly 1 leaves it untouched. Any other
     gate is *dense*: the matching entries that share every non-target digit form a slice, and the
@@ -62,11 +63,11 @@ def basis(dims: Sequence[int], values: Sequence[int] | None = None):
 
 
 def gate_class(U) -> Tuple[str, np.ndarray, np.ndarray]:
-    """("monomial", rows, values) when every column has exactly one entry that is not exactly
-    zero, else ("dense", None, None)."""
+    """("monomial", rows, values) when every column and every row has exactly one entry that is
+    not exactly zero, else ("dense", None, None)."""
     U = np.asarray(U, dtype=np.complex128)
     nz = (U.real != 0) | (U.imag != 0)
-    if np.all(nz.sum(axis=0) == 1):
+    if np.all(nz.sum(axis=0) == 1) and np.all(nz.sum(axis=1) == 1):
         rows = np.argmax(nz, axis=0)
         return "monomial", rows, U[rows, np.arange(U.shape[1])]
     return "dense", None, None

@@ -162,6 +162,8 @@ def test_gate_classes():
     assert kind == "monomial" and np.all(vals == 1.0)
     assert S.gate_class(O.f_gate(3))[0] == "dense"
     assert S.gate_class(C.haar_unitary(4, np.random.default_rng(0)))[0] == "dense"
+    # one entry per column but two in a row (not unitary): would merge two indices, so dense
+    assert S.gate_class(np.array([[1, 1], [0, 0]], dtype=np.complex128))[0] == "dense"
 
 
 def test_swap_exchanges_digits_and_phases_multiply():
