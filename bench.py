@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
     ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend",
+    ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend,sparse",
                     help="comma list of extras: copy, qft, brick, batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -324,6 +324,127 @@ def bench_frontend(Q, n_q=20, n_g=200_000, seed=7):
             "moments_ms_incl_binding": t_mom * 1e3, "depth": depth}
 
 
+def _lib_network(Q, net, dims):
+    """A Toffoli network as a library circuit, decomposed by the library's front-end (Sec. 3.4)."""
+    c = Q.qd_circuit_create(dims)
+    for g in net:
+        Q.qd_circuit_add(c, Q.QD_GATE_X, g.targets[0], g.a, g.controls, g.cvals)
+    dc = Q.qd_circuit_decompose(c)
+    Q.qd_circuit_free(c)
+    return dc
+
+
+def bench_sparse(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
+    """Sparse state on a permutation-heavy workload: a 600-gate Toffoli network, decomposed through
+    intermediate qutrits, over the 2^24 superposed inputs of a 32-qubit + 8-qutrit register
+    (D = 2^32 3^8, beyond any dense state). A second network on a register that fits the dense
+    complex128 path is timed both ways. Algorithmic bytes of a monomial launch: every index read
+    (8 B) and every moved index written (8 B); the moved count is the library's update counter."""
+    import numpy as np
+    import circuits as C
+    st = torch.cuda.current_stream().cuda_stream
+    tn = C.toffoli_network(32, 8, 16, 600, C.seeded_rng(1005))
+    sp = Q.qd_sparse_init(tn.dims, 1 << 24, st)
+    e0, e1 = _ev(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for g in tn.inputs:
+        Q.apply_circuit_gate_sparse(sp, g, tn.dims)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inputs = e0.elapsed_time(e1)
+    n = Q.qd_sparse_count(sp)
+    dc = _lib_network(Q, tn.network, tn.dims)
+    ng = Q.qd_circuit_size(dc)[1]
+    Q.qd_circuit_apply_sparse(sp, dc)                  # warm-up (the network is a permutation)
+    u0 = Q.qd_sparse_updates(sp)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        Q.qd_circuit_apply_sparse(sp, dc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    upd = (Q.qd_sparse_updates(sp) - u0) / reps
+    assert Q.qd_sparse_count(sp) == n and abs(Q.qd_sparse_norm2(sp) - 1.0) < 1e-12
+    Q.qd_sparse_free(sp)
+    Q.qd_circuit_free(dc)
+    alg_bytes = 8.0 * n * ng + 8.0 * upd
+    big = {"workload": "Toffoli network, 600 gates (decomposed: %d) on 32 qubits + 8 qutrits, 2^24 entries" % ng,
+           "D": 2 ** 32 * 3 ** 8, "entries": n, "gates": ng, "inputs_ms": t_inputs, "network_ms": ms,
+           "gates_per_s": ng / (ms * 1e-3), "entries_per_s": n * ng / (ms * 1e-3),
+           "amp_upd_per_s": upd / (ms * 1e-3), "updates_per_network": upd,
+           "roofline": {"bound": "hbm", "kernel": "k_monomial<true>", "achieved": alg_bytes / (ms * 1e-3) / 1e9,
+                        "peak": 8000.0, "unit": "GB/s", "frac": alg_bytes / (ms * 1e-3) / 1e9 / 8000.0,
+                        "bytes_per_network": alg_bytes}}
+    # a register the dense path holds: 20 qubits + 4 qutrits (D = 2^20 3^4), 2^16 entries
+    tn2 = C.toffoli_network(20, 4, 12, 300, C.seeded_rng(1006))
+    dc2 = _lib_network(Q, tn2.network, tn2.dims)
+    ng2 = Q.qd_circuit_size(dc2)[1]
+    sp = Q.qd_sparse_init(tn2.dims, 1 << 16, st)
+    s = Q.qd_state_init(tn2.dims, Q.QD_C128, st)
+    for g in tn2.inputs:
+        Q.apply_circuit_gate_sparse(sp, g, tn2.dims)
+        Q.apply_circuit_gate(s, g, tn2.dims)
+    Q.qd_circuit_apply_sparse(sp, dc2)
+    Q.qd_circuit_apply(s, dc2)
+    torch.cuda.synchronize()
+    e0.record()
+    Q.qd_circuit_apply_sparse(sp, dc2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_sp = e0.elapsed_time(e1)
+    e0.record()
+    Q.qd_circuit_apply(s, dc2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_dense = e0.elapsed_time(e1)
+    chk = Q.qd_state_init(tn2.dims, Q.QD_C128, st)
+    Q.qd_sparse_to_dense(sp, chk)
+    diff = float(np.max(np.abs(Q.qd_state_download(chk) - Q.qd_state_download(s))))
+    n2 = Q.qd_sparse_count(sp)
+    for h in (chk, s):
+        Q.qd_state_free(h)
+    Q.qd_sparse_free(sp)
+    Q.qd_circuit_free(dc2)
+    small = {"workload": "Toffoli network, 300 gates (decomposed: %d) on 20 qubits + 4 qutrits, 2^16 entries" % ng2,
+             "D": 2 ** 20 * 3 ** 4, "entries": n2, "sparse_ms": ms_sp, "dense_c128_ms": ms_dense,
+             "speedup_vs_dense": ms_dense / ms_sp, "max_abs_vs_dense": diff}
+    out = {"big": big, "vs_dense": small}
+    if cpu:
+        out["cpu_oracle"] = bench_sparse_cpu(tn, cpu_seconds)
+    return out
+
+
+def bench_sparse_cpu(tn, seconds):
+    """The sparse oracle (never tuned) on a bounded sample of the big network's workload: 2^16 of
+    its input basis states walked through the decomposed network until `seconds` are spent."""
+    import numpy as np
+    import oracle as O
+    from oracle import frontend as F
+    from oracle import sparse as S
+    dims = tn.dims
+    gates = F.decompose_circuit(dims, [("X", g.targets[0], g.a, tuple(g.controls), tuple(g.cvals)) for g in tn.network])
+    st = O.strides(dims)
+    rng = np.random.default_rng(3)
+    bits = rng.integers(0, 2, size=(1 << 16, 24))
+    wires = list(range(16)) + list(range(32, 40))
+    idx = np.unique((bits * np.array([st[q] for q in wires], dtype=np.int64)).sum(axis=1))
+    amp = np.full(idx.size, 2.0 ** -12 + 0j)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _, t, a, ctl, cv in gates:
+            idx, amp = S.apply_gate(dims, idx, amp, (t,), ctl, cv, O.x_gate(dims[t], a))
+            done += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done * idx.size / dt, "unit": "entries/s (entries processed per gate)", "cores": 1,
+            "kind": "oracle", "sample": f"{idx.size} entries of the same register through {done} decomposed gates, "
+                                        f"NumPy, 1 thread, {dt:.1f} s"}
+
+
 def bench_batch(Q, torch, ncirc=4096):
     """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
     layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
@@ -469,6 +590,13 @@ def main():
         extras["measurement_hybrid20q"] = mm
         log(f"measurement: {mm['shots']} shots in {mm['sample_ms']:.2f} ms ({mm['shots_per_s']:.3e} shots/s), "
             f"marginals {mm['marginals_ms']:.2f} ms, support count {mm['support_count_ms']:.2f} ms")
+    if "sparse" in which:
+        sp = bench_sparse(Q, torch, cpu=not args.no_cpu, cpu_seconds=min(args.cpu_seconds, 10.0))
+        extras["sparse_toffoli_network"] = sp
+        b = sp["big"]
+        log(f"sparse: {b['entries']} entries x {b['gates']} gates in {b['network_ms']:.2f} ms "
+            f"({b['entries_per_s']:.3e} entries/s, {b['roofline']['achieved']:.0f} GB/s alg.), "
+            f"x{sp['vs_dense']['speedup_vs_dense']:.0f} vs dense c128 on the 2^16-entry network")
     if tuning:
         extras["tuning"] = tuning
     out = {

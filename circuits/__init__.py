@@ -28,6 +28,7 @@ __all__ = [
     "Gate", "Circuit", "haar_unitary", "random_basis_superposition",
     "config0", "config1", "config1_shrink", "config2", "config3", "config4",
     "random_gate", "random_circuit", "permutation_circuit", "diagonal_circuit", "seeded_rng",
+    "qubit_hadamard_on_qutrit", "ToffoliNetwork", "toffoli_network",
 ]
 
 
@@ -306,3 +307,51 @@ def config4(nc: int = 4096, ngates: int = 100, seed: int = 1004) -> List[Circuit
         gates = [random_gate(dims, rng, kinds=("X", "Z", "F", "CX", "H1")) for _ in range(ngates)]
         out.append(Circuit(dims, gates, name=f"cfg4-{i}"))
     return out
+
+
+# --------------------------------------------------------------------------------------------
+# permutation-heavy workload for the sparse state
+# --------------------------------------------------------------------------------------------
+def qubit_hadamard_on_qutrit() -> np.ndarray:
+    """3x3 unitary acting as the Hadamard on levels {0, 1} of a qutrit and fixing level 2 (an
+    explicit gate, so each consumer applies it as given)."""
+    c = 1.0 / math.sqrt(2.0)
+    return np.array([[c, c, 0.0], [c, -c, 0.0], [0.0, 0.0, 1.0]], dtype=np.complex128)
+
+
+@dataclass
+class ToffoliNetwork:
+    """A reversible Toffoli network on qubit wires plus qutrit wires that carry logical bits and
+    serve as the intermediate-level control of each Toffoli (the paper's multiplier and RevLib
+    circuits, Sec. 3.4 and 6, decomposed through intermediate qutrits).
+
+    dims: qubits first, then qutrits. inputs: the superposition-preparing layer (F on the first
+    n_in qubits, the embedded Hadamard on every qutrit), so 2^(n_in + n_qutrits) basis states are
+    present. network: named X gates with 0, 1 or 2 controls, all control values 1 and every target
+    a qubit; a 2-control gate has a qutrit as its second control (so it has a free level)."""
+    dims: tuple
+    inputs: List[Gate]
+    network: List[Gate]
+
+
+def toffoli_network(n_qubits: int, n_qutrits: int, n_in: int, ngates: int, rng: np.random.Generator,
+                    p_toffoli: float = 0.5, p_cx: float = 0.3) -> ToffoliNetwork:
+    dims = (2,) * n_qubits + (3,) * n_qutrits
+    qubits = list(range(n_qubits))
+    qutrits = list(range(n_qubits, n_qubits + n_qutrits))
+    h3 = qubit_hadamard_on_qutrit()
+    inputs = [Gate("F", (q,)) for q in range(n_in)] + [Gate("U", (q,), U=h3, tag="h01") for q in qutrits]
+    net = []
+    for _ in range(ngates):
+        r = rng.random()
+        t = int(rng.choice(qubits))
+        if r < p_toffoli and qutrits:
+            c2 = int(rng.choice(qutrits))
+            c1 = int(rng.choice([q for q in range(len(dims)) if q not in (t, c2)]))
+            net.append(Gate("X", (t,), (c1, c2), (1, 1), a=1))
+        elif r < p_toffoli + p_cx:
+            c = int(rng.choice([q for q in range(len(dims)) if q != t]))
+            net.append(Gate("X", (t,), (c,), (1,), a=1))
+        else:
+            net.append(Gate("X", (t,), a=1))
+    return ToffoliNetwork(dims, inputs, net)

@@ -344,6 +344,87 @@ int qd_circuit_apply(qd_state* s, const qd_circuit* c);
 
 void qd_circuit_free(qd_circuit* c);
 
+/* ---------------------------------------------------------------- sparse state (Sec. 3.3, 3.7) */
+
+/* A state kept as the list of its non-zero amplitudes (complex128) with their flat indices (int64),
+ * the compressed sparse column of Sec. 3.3 and the sparse backends of Sec. 3.7, updated gate by
+ * gate on the GPU. The register may be far larger than any dense state (D up to 2^63 - 1); the
+ * list holds at most 2^31 - 1 entries.
+ *
+ * Rules:
+ *  - an index is present exactly when its amplitude is not exactly zero: a dense-gate output whose
+ *    real and imaginary parts are both 0.0 is dropped (sparse products store no exact zeros);
+ *    entries moved by a monomial gate are kept;
+ *  - a monomial gate (exactly one non-zero entry in every row and column of U: X_{+a}, generalized
+ *    CNOTs, Z_d, controlled phases, qudit swaps) moves each matching entry where it stands: column
+ *    loc goes to the row r of its entry and the amplitude is multiplied by U[r, loc] unless that
+ *    entry is exactly 1. It never changes the count and never waits on the host;
+ *  - any other gate is dense: the matching entries that share every non-target digit form a slice,
+ *    and the slice's d_T outputs are U times its d_T inputs (absent inputs are zero). A product
+ *    u x is (ur xr - ui xi, ur xi + ui xr) and an output sums j = 0..d_T-1 in order from +0.0, each
+ *    real operation rounded on its own, so results are bitwise reproducible;
+ *  - list order: a monomial gate keeps every position; a dense gate keeps the non-matching entries
+ *    in order and writes each slice's non-zero outputs, by increasing local row, where the slice's
+ *    first entry stood.
+ * Calls are asynchronous on the state's stream except where noted. Overlapping calls on one state
+ * from several threads are not allowed. */
+typedef struct qd_sparse qd_sparse;
+
+/* Sparse |0...0> (one entry, amplitude 1) on dims[0..n-1]. capacity: initial entries per list
+ * buffer (0 = 65536; the lists grow by themselves). QD_EINVAL / QD_EDIM / QD_EOVERFLOW as for a
+ * register, QD_ENOMEM if the device allocation fails. Synchronises. */
+int qd_sparse_init(const int32_t* dims, int32_t n, int64_t capacity, void* hip_stream, qd_sparse** out);
+
+/* Replace the list by `count` host entries: idx[e] (distinct, 0..D-1) and amps[2e], amps[2e+1]
+ * (finite, not both zero). QD_EINVAL otherwise (the state is unchanged). Synchronises. */
+int qd_sparse_upload(qd_sparse* s, const int64_t* idx, const double* amps, int64_t count);
+
+/* One basis state (values[i] in 0..d_i-1), amplitude 1. Synchronises. */
+int qd_sparse_set_basis(qd_sparse* s, const int32_t* values);
+
+/* Apply a (controlled) k-qudit gate: arguments and validation exactly as qd_apply_gate_ex (all
+ * checks before any device work; a failed call leaves the list unchanged). A dense gate waits once
+ * on the host for its slice count. */
+int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const int32_t* control_values, int32_t m, const double* U, uint32_t flags);
+
+/* Number of entries. Synchronises. */
+int qd_sparse_count(qd_sparse* s, int64_t* out);
+
+/* Copy the list (list order) to host arrays of `cap` entries (idx: int64, amps: interleaved
+ * doubles). *count receives the number of entries; QD_EINVAL if cap is smaller (nothing copied).
+ * Synchronises. */
+int qd_sparse_download(qd_sparse* s, int64_t* idx, double* amps, int64_t cap, int64_t* count);
+
+/* Device addresses of the current list and its count, valid until the next qd_sparse_* call on s.
+ * Synchronises. */
+int qd_sparse_device_lists(qd_sparse* s, int64_t** idx, double** amps, int64_t* count);
+
+/* Sum of |a|^2 over the entries in FP64 (fixed reduction order for a given count). Synchronises. */
+int qd_sparse_norm2(qd_sparse* s, double* out);
+
+/* |a_e|^2 per entry in list order (re^2 + im^2, each operation rounded) into out (cap entries,
+ * device memory when out_is_device). QD_EINVAL if cap is smaller than the count. Synchronises. */
+int qd_sparse_probabilities(qd_sparse* s, double* out, int32_t out_is_device, int64_t cap);
+
+/* Write the state into a dense state of the same register (zeros elsewhere; rounded to complex64
+ * for a QD_C64 state). QD_EDIM if the registers differ. Synchronises. */
+int qd_sparse_to_dense(qd_sparse* s, qd_state* dst);
+
+/* Entries written by gates since the state was created: a monomial gate counts its matching
+ * entries, a dense gate the outputs it writes for its slices (the amplitude updates of the
+ * throughput figures). Synchronises. */
+int qd_sparse_updates(qd_sparse* s, int64_t* out);
+
+/* Wait for the state's queued work. */
+int qd_sparse_sync(qd_sparse* s);
+
+/* Apply a circuit's gates in order to a sparse state of the same register (qd_sparse_apply_gate
+ * for each). QD_EDIM if the registers differ. */
+int qd_circuit_apply_sparse(qd_sparse* s, const qd_circuit* c);
+
+void qd_sparse_free(qd_sparse* s);
+
 /* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
 
 /* nc independent registers in one device arena: circuit c has n_per[c] qudits whose dims follow

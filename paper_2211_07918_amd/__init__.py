@@ -35,7 +35,10 @@ __all__ = [
     "qd_normalize", "qd_sample", "qd_sample_device", "qd_marginals", "qd_support", "qd_ket_string", "kets",
     "qd_circuit_create", "qd_circuit_add", "qd_qasm_parse", "qd_circuit_size", "qd_circuit_dims", "qd_circuit_name",
     "qd_circuit_gate", "qd_circuit_gates", "qd_circuit_moments", "qd_circuit_decompose", "qd_circuit_apply",
-    "qd_circuit_free",
+    "qd_circuit_free", "qd_circuit_apply_sparse",
+    "qd_sparse_init", "qd_sparse_upload", "qd_sparse_set_basis", "qd_sparse_apply_gate", "qd_sparse_count",
+    "qd_sparse_download", "qd_sparse_device_lists", "qd_sparse_norm2", "qd_sparse_probabilities",
+    "qd_sparse_to_dense", "qd_sparse_updates", "qd_sparse_sync", "qd_sparse_free", "apply_circuit_gate_sparse",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
     "qd_batch_apply_layer", "qd_batch_capture", "qd_batch_replay", "qd_batch_download",
     "qd_batch_free", "qd_tune_set", "qd_tune_get", "qd_autotune", "qd_tune_load", "qd_tune_save", "qd_batch_autotune",
@@ -127,6 +130,20 @@ _SIGS = {
     "qd_circuit_decompose": (C.c_int, [_P, C.POINTER(_P)]),
     "qd_circuit_apply": (C.c_int, [_P, _P]),
     "qd_circuit_free": (None, [_P]),
+    "qd_circuit_apply_sparse": (C.c_int, [_P, _P]),
+    "qd_sparse_init": (C.c_int, [_I32P, C.c_int32, C.c_int64, _P, C.POINTER(_P)]),
+    "qd_sparse_upload": (C.c_int, [_P, _P, _P, C.c_int64]),
+    "qd_sparse_set_basis": (C.c_int, [_P, _I32P]),
+    "qd_sparse_apply_gate": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
+    "qd_sparse_count": (C.c_int, [_P, _I64P]),
+    "qd_sparse_download": (C.c_int, [_P, _P, _P, C.c_int64, _I64P]),
+    "qd_sparse_device_lists": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), _I64P]),
+    "qd_sparse_norm2": (C.c_int, [_P, _DP]),
+    "qd_sparse_probabilities": (C.c_int, [_P, _P, C.c_int32, C.c_int64]),
+    "qd_sparse_to_dense": (C.c_int, [_P, _P]),
+    "qd_sparse_sync": (C.c_int, [_P]),
+    "qd_sparse_updates": (C.c_int, [_P, _I64P]),
+    "qd_sparse_free": (None, [_P]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
     "qd_batch_offset": (C.c_int, [_P, C.c_int32, _I64P]),
@@ -572,6 +589,100 @@ def qd_circuit_apply(s: int, c: int) -> None:
 
 def qd_circuit_free(c: int) -> None:
     load().qd_circuit_free(_P(c))
+
+
+def qd_circuit_apply_sparse(sp: int, c: int) -> None:
+    _check(load().qd_circuit_apply_sparse(_P(sp), _P(c)))
+
+
+# ------------------------------------------------------------------------------ sparse state
+_SPARSE_DIMS = {}   # handle -> register, for the argument-shape check before a raw pointer is passed
+
+
+def qd_sparse_init(dims, capacity: int = 0, stream: int = 0) -> int:
+    out = _P()
+    _check(load().qd_sparse_init(_i32(dims), len(dims), int(capacity), _P(stream), C.byref(out)))
+    _SPARSE_DIMS[out.value] = [int(d) for d in dims]
+    return out.value
+
+
+def qd_sparse_upload(sp: int, idx, amps) -> None:
+    i = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128))
+    if i.shape != a.shape:
+        raise ValueError("idx and amps must have the same length")
+    _check(load().qd_sparse_upload(_P(sp), i.ctypes.data_as(_P), a.ctypes.data_as(_P), i.size))
+
+
+def qd_sparse_set_basis(sp: int, values) -> None:
+    _check(load().qd_sparse_set_basis(_P(sp), _i32(values)))
+
+
+def qd_sparse_apply_gate(sp: int, targets, controls, control_values, U, flags: int = 0) -> None:
+    Uc = _cplx(U)
+    _check_shape(_SPARSE_DIMS[sp], targets, Uc)
+    _check(load().qd_sparse_apply_gate(_P(sp), _i32(targets), len(targets), _i32(controls), _i32(control_values),
+                                       len(controls), _dptr(Uc), int(flags)))
+
+
+def apply_circuit_gate_sparse(sp: int, gate, dims, flags: int = 0):
+    """qd_sparse_apply_gate for one gate record."""
+    qd_sparse_apply_gate(sp, gate.targets, gate.controls, gate.cvals, gate_unitary(gate, dims), flags)
+
+
+def qd_sparse_count(sp: int) -> int:
+    n = C.c_int64()
+    _check(load().qd_sparse_count(_P(sp), C.byref(n)))
+    return int(n.value)
+
+
+def qd_sparse_download(sp: int):
+    """The list in list order: (indices int64, amplitudes complex128)."""
+    n = qd_sparse_count(sp)
+    idx = np.empty(n, dtype=np.int64)
+    amps = np.empty(n, dtype=np.complex128)
+    cnt = C.c_int64()
+    _check(load().qd_sparse_download(_P(sp), idx.ctypes.data_as(_P), amps.ctypes.data_as(_P), n, C.byref(cnt)))
+    return idx, amps
+
+
+def qd_sparse_device_lists(sp: int):
+    """(device address of the indices, of the amplitudes, count)."""
+    pi, pa, n = _P(), _P(), C.c_int64()
+    _check(load().qd_sparse_device_lists(_P(sp), C.byref(pi), C.byref(pa), C.byref(n)))
+    return pi.value, pa.value, int(n.value)
+
+
+def qd_sparse_norm2(sp: int) -> float:
+    v = C.c_double()
+    _check(load().qd_sparse_norm2(_P(sp), C.byref(v)))
+    return float(v.value)
+
+
+def qd_sparse_probabilities(sp: int) -> np.ndarray:
+    n = qd_sparse_count(sp)
+    out = np.empty(n, dtype=np.float64)
+    _check(load().qd_sparse_probabilities(_P(sp), out.ctypes.data_as(_P), 0, n))
+    return out
+
+
+def qd_sparse_to_dense(sp: int, s: int) -> None:
+    _check(load().qd_sparse_to_dense(_P(sp), _P(s)))
+
+
+def qd_sparse_updates(sp: int) -> int:
+    n = C.c_int64()
+    _check(load().qd_sparse_updates(_P(sp), C.byref(n)))
+    return int(n.value)
+
+
+def qd_sparse_sync(sp: int) -> None:
+    _check(load().qd_sparse_sync(_P(sp)))
+
+
+def qd_sparse_free(sp: int) -> None:
+    _SPARSE_DIMS.pop(sp, None)
+    load().qd_sparse_free(_P(sp))
 
 
 # ------------------------------------------------------------------------------ batch

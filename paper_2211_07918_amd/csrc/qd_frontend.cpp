@@ -318,6 +318,26 @@ int qd_circuit_apply(qd_state* s, const qd_circuit* c) {
   return QD_OK;
 }
 
+int qd_circuit_apply_sparse(qd_sparse* s, const qd_circuit* c) {
+  if (!s || !c) return fail(QD_EINVAL, "null argument");
+  const Register& r = sparse_register(s);
+  const std::vector<int32_t> sd(r.dims, r.dims + r.n);
+  if (sd != c->dims) return fail(QD_EDIM, "circuit register differs from the state's");
+  std::vector<SparseGate> seq(c->gates.size());
+  for (size_t i = 0; i < c->gates.size(); ++i) {
+    const qd_circuit::G& g = c->gates[i];
+    const int d = c->dims[size_t(g.target)];
+    SparseGate& q = seq[i];
+    q.t = {g.target};
+    q.c = g.ctl;
+    q.v = g.cval;
+    q.U.assign(2 * size_t(d) * size_t(d), 0.0);
+    int rc = qd_gate_matrix(g.kind, d, g.kind == QD_GATE_X ? g.a : 0, q.U.data());
+    if (rc) return rc;
+  }
+  return sparse_apply_gates(s, seq.data(), seq.size(), 0);
+}
+
 void qd_circuit_free(qd_circuit* c) { delete c; }
 
 }  // extern "C"

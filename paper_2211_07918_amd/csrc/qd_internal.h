@@ -158,6 +158,15 @@ struct TileGeom {
 bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g);
 int route_gate(const Register& r, int prec, const GatePlan& p);
 
+// Sparse state (qd_sparse.hip): its register, and a gate sequence applied with one parameter
+// upload per run of monomial gates (all gates validated first; flags as qd_apply_gate_ex)
+const Register& sparse_register(const qd_sparse* s);
+struct SparseGate {
+  std::vector<int32_t> t, c, v;   // targets, controls, control values
+  std::vector<double> U;          // d_T x d_T, row-major, interleaved
+};
+int sparse_apply_gates(qd_sparse* s, const SparseGate* gates, size_t count, uint32_t flags);
+
 // Launchers (qd_gates.hip)
 int launch_gate(qd_state* s, const GatePlan& p);
 int launch_fill_basis(qd_state* s, int64_t index);

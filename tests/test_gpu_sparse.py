@@ -1,0 +1,297 @@
+"""GPU sparse state (qd_sparse_*) against the sparse oracle.
+
+Entry lists are compared element by element in list order: indices exactly, amplitudes exactly
+(both sides form every product and every sum in the same order with each real operation rounded on
+its own). The two sides build their named-gate matrices separately and those can differ only in
+the sign of a zero entry, so amplitudes are compared part by part with ==, under which +0.0 and -0.0
+are equal. Full-size Toffoli networks (2^24 entries on a 2^32 x 3^8 register, far beyond any dense
+state) are checked against the oracle on sampled basis states and by properties that hold at any
+size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+from oracle import frontend as F
+from oracle import sparse as S
+import paper_2211_07918_amd as Q
+from gpu_util import max_abs, run_gpu, torch_stream
+from test_oracle_sparse import _digit_walk, _flat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stream():
+    return torch_stream()
+
+
+def same_list(got, want):
+    gi, ga = got
+    wi, wa = want
+    assert gi.tolist() == wi.tolist()
+    assert np.all(ga.real == wa.real) and np.all(ga.imag == wa.imag)
+
+
+def nonzero_entries(psi):
+    """Upload arrays for an explicit initial state (plain data: the non-zero positions)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    idx = np.flatnonzero(psi != 0).astype(np.int64)
+    return idx, psi[idx]
+
+
+def run_sparse(dims, gates, stream, init=None, capacity=0, basis=None):
+    sp = Q.qd_sparse_init(dims, capacity, stream)
+    try:
+        if init is not None:
+            Q.qd_sparse_upload(sp, *init)
+        if basis is not None:
+            Q.qd_sparse_set_basis(sp, basis)
+        for g in gates:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        return Q.qd_sparse_download(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_circuits_match_the_oracle_exactly(stream, seed):
+    rng = np.random.default_rng(100 + seed)
+    dims = [int(x) for x in rng.integers(2, 5, size=int(rng.integers(3, 8)))]
+    circ = C.random_circuit(dims, 30, rng, max_targets=2, max_controls=2)
+    same_list(run_sparse(dims, circ.gates, stream), S.run_circuit(circ))
+
+
+def test_three_target_gates_from_a_superposition(stream):
+    rng = np.random.default_rng(7)
+    dims = (2, 3, 2, 4, 3)
+    psi0 = C.random_basis_superposition(int(np.prod(dims)), 40, rng)
+    gates = [C.Gate("U", (4, 0, 2), (1,), (2,), U=C.haar_unitary(12, rng)),
+             C.Gate("U", (3,), (0, 2), (1, 0), U=C.haar_unitary(4, rng)),
+             C.Gate("X", (1,), (3,), (2,), a=2), C.Gate("Z", (3,), (1,), (1,))]
+    circ = C.Circuit(dims, gates, init_amps=psi0)
+    same_list(run_sparse(dims, gates, stream, init=nonzero_entries(psi0)), S.run_circuit(circ))
+
+
+@pytest.mark.parametrize("d,n", [(2, 5), (3, 4), (4, 3), (5, 3)])
+def test_generalized_ghz(stream, d, n):
+    dims = (d,) * n
+    gates = [C.Gate("F", (0,))] + [C.Gate("X", (k,), (0,), (v,), a=v) for k in range(1, n) for v in range(1, d)]
+    idx, amp = run_sparse(dims, gates, stream)
+    step = sum(d ** (n - 1 - q) for q in range(n))
+    assert idx.tolist() == [j * step for j in range(d)]
+    assert np.all(amp == complex(1.0 / math.sqrt(d), 0.0))
+
+
+def test_cancellation_drops_the_entry(stream):
+    idx, amp = run_sparse((2, 3), [C.Gate("F", (0,)), C.Gate("F", (0,))], stream)
+    assert idx.tolist() == [0] and abs(amp[0] - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("dims", [(3,) * 39, (2,) * 62, (2, 3, 4, 5, 7) * 5])
+def test_permutation_walk_on_huge_registers(stream, dims):
+    rng = np.random.default_rng(len(dims))
+    circ = C.permutation_circuit(dims, 300, rng)
+    start = tuple(int(rng.integers(0, d)) for d in dims)
+    idx, amp = run_sparse(dims, circ.gates, stream, basis=start)
+    assert idx.tolist() == [_flat(dims, _digit_walk(dims, circ.gates, start))]
+    assert amp.tolist() == [1.0 + 0.0j]
+
+
+def test_lists_grow_from_a_tiny_capacity(stream):
+    dims = (2,) * 14 + (3,) * 2
+    gates = [C.Gate("F", (q,)) for q in range(12)] + [C.Gate("F", (14,)), C.Gate("Z", (15,))]
+    gates += [C.Gate("X", (q,), (q + 1,), (1,), a=1) for q in range(13)]
+    circ = C.Circuit(dims, gates)
+    got = run_sparse(dims, gates, stream, capacity=16)
+    assert len(got[0]) == 2 ** 12 * 3
+    same_list(got, S.run_circuit(circ))
+
+
+def test_empty_list_and_unmatched_dense_gate(stream):
+    dims = (3, 3, 2)
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_upload(sp, [], [])
+        Q.qd_sparse_apply_gate(sp, (0,), (), (), O.f_gate(3))
+        Q.qd_sparse_apply_gate(sp, (1,), (), (), O.x_gate(3, 1))
+        assert Q.qd_sparse_count(sp) == 0 and Q.qd_sparse_norm2(sp) == 0.0
+        # a dense gate whose control matches no entry leaves the list as it was
+        Q.qd_sparse_set_basis(sp, (1, 2, 0))
+        Q.qd_sparse_apply_gate(sp, (0,), (2,), (1,), O.f_gate(3))
+        idx, amp = Q.qd_sparse_download(sp)
+        assert idx.tolist() == [1 * 6 + 2 * 2] and amp.tolist() == [1.0]
+    finally:
+        Q.qd_sparse_free(sp)
+
+
+def test_invalid_arguments_leave_the_state_unchanged(stream):
+    dims = (2, 3)
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_apply_gate(sp, (1,), (), (), O.f_gate(3))
+        before = Q.qd_sparse_download(sp)
+        for idx, amps in (([0, 0], [1, 1]), ([6], [1]), ([-1], [1]), ([2], [0.0]), ([2], [np.nan])):
+            with pytest.raises(Q.QDError) as e:
+                Q.qd_sparse_upload(sp, np.array(idx), np.array(amps, dtype=np.complex128))
+            assert e.value.code == Q.QD_EINVAL
+        with pytest.raises(Q.QDError):
+            Q.qd_sparse_apply_gate(sp, (0,), (0,), (1,), O.x_gate(2))        # control repeats the target
+        with pytest.raises(Q.QDError):
+            Q.qd_sparse_apply_gate(sp, (0,), (), (), 2 * O.x_gate(2))        # not unitary
+        with pytest.raises(Q.QDError):
+            Q.qd_sparse_set_basis(sp, (0, 3))
+        same_list(Q.qd_sparse_download(sp), before)
+    finally:
+        Q.qd_sparse_free(sp)
+
+
+def test_norm_and_probabilities(stream):
+    rng = np.random.default_rng(11)
+    dims = (3, 2, 4, 3, 2, 2)
+    circ = C.random_circuit(dims, 25, rng)
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        for g in circ.gates:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        idx, amp = S.run_circuit(circ)
+        p = Q.qd_sparse_probabilities(sp)
+        want = amp.real * amp.real + amp.imag * amp.imag
+        assert np.array_equal(p, want)
+        assert abs(Q.qd_sparse_norm2(sp) - S.norm2(amp)) <= 1e-14
+    finally:
+        Q.qd_sparse_free(sp)
+
+
+@pytest.mark.parametrize("prec,tol", [(Q.QD_C128, 1e-12), (Q.QD_C64, 1e-6)])
+def test_scatter_matches_the_dense_gpu_path(stream, prec, tol):
+    rng = np.random.default_rng(21)
+    dims = (2, 3, 4, 2, 3, 2, 2, 3)
+    circ = C.random_circuit(dims, 40, rng)
+    dense = run_gpu(circ, Q.QD_C128, stream)
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    s = Q.qd_state_init(dims, prec, stream)
+    try:
+        for g in circ.gates:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        Q.qd_sparse_to_dense(sp, s)
+        assert max_abs(Q.qd_state_download(s), dense) <= tol
+    finally:
+        Q.qd_sparse_free(sp)
+        Q.qd_state_free(s)
+
+
+def lib_network(net, dims):
+    """The network as a library circuit (multi-controlled X given as such), decomposed by the library."""
+    c = Q.qd_circuit_create(dims)
+    try:
+        for g in net:
+            Q.qd_circuit_add(c, Q.QD_GATE_X, g.targets[0], g.a, g.controls, g.cvals)
+        return Q.qd_circuit_decompose(c)
+    finally:
+        Q.qd_circuit_free(c)
+
+
+def oracle_network(net, dims):
+    gates = F.decompose_circuit(dims, [("X", g.targets[0], g.a, tuple(g.controls), tuple(g.cvals)) for g in net])
+    return [C.Gate("X", (t,), tuple(ctl), tuple(cv), a=a) for _, t, a, ctl, cv in gates]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_toffoli_network_through_the_front_end(stream, seed):
+    rng = np.random.default_rng(300 + seed)
+    tn = C.toffoli_network(12, 3, 6, 200, rng)
+    sp = Q.qd_sparse_init(tn.dims, 0, stream)
+    dc = lib_network(tn.network, tn.dims)
+    try:
+        for g in tn.inputs:
+            Q.apply_circuit_gate_sparse(sp, g, tn.dims)
+        Q.qd_circuit_apply_sparse(sp, dc)
+        got = Q.qd_sparse_download(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+        Q.qd_circuit_free(dc)
+    idx, amp = S.run_circuit(C.Circuit(tn.dims, tn.inputs))
+    idx, amp = S.run_circuit(C.Circuit(tn.dims, oracle_network(tn.network, tn.dims)), idx, amp)
+    assert len(idx) == 2 ** 9
+    same_list(got, (idx, amp))
+
+
+def test_circuit_register_must_match(stream):
+    sp = Q.qd_sparse_init((2, 3), 0, stream)
+    c = Q.qd_circuit_create((3, 2))
+    try:
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_circuit_apply_sparse(sp, c)
+        assert e.value.code == Q.QD_EDIM
+    finally:
+        Q.qd_sparse_free(sp)
+        Q.qd_circuit_free(c)
+
+
+def test_full_size_network_sampled(stream):
+    """The benchmark's shape: 32 qubits + 8 qutrits (D = 2^32 3^8), 16 superposed input qubits and
+    the 8 qutrits' logical bits: 2^24 entries through a 600-gate Toffoli network."""
+    rng = C.seeded_rng(1005)
+    tn = C.toffoli_network(32, 8, 16, 600, rng)
+    dims = tn.dims
+    sp = Q.qd_sparse_init(dims, 1 << 24, stream)
+    dc = lib_network(tn.network, dims)
+    try:
+        for g in tn.inputs:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        assert Q.qd_sparse_count(sp) == 1 << 24
+        Q.qd_circuit_apply_sparse(sp, dc)
+        idx, amp = Q.qd_sparse_download(sp)
+        norm = Q.qd_sparse_norm2(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+        Q.qd_circuit_free(dc)
+    # properties: distinct indices, one common amplitude of modulus 2^-12, unit norm
+    assert len(idx) == 1 << 24
+    order = np.argsort(idx)
+    si = idx[order]
+    assert np.all(np.diff(si) > 0)
+    assert np.all(amp == amp[0]) and abs(abs(amp[0]) - 2.0 ** -12) < 1e-15 and abs(norm - 1.0) < 1e-12
+    # sampled basis states of the input superposition, walked through the network by the oracle
+    srng = np.random.default_rng(5)
+    st = O.strides(dims)
+    n_in = 16
+    ins = []
+    for _ in range(2048):
+        bits = srng.integers(0, 2, size=n_in + 8)
+        x = sum(int(b) * st[q] for b, q in zip(bits[:n_in], range(n_in)))
+        x += sum(int(b) * st[32 + j] for j, b in enumerate(bits[n_in:]))
+        ins.append(x)
+    ins = np.unique(np.array(ins, dtype=np.int64))
+    oi, _ = S.run_circuit(C.Circuit(dims, oracle_network(tn.network, dims)), ins, np.ones(ins.size, dtype=np.complex128))
+    pos = np.searchsorted(si, oi)
+    assert np.all(pos < si.size) and np.array_equal(si[np.minimum(pos, si.size - 1)], oi)
+
+
+def test_update_counter(stream):
+    """A permutation walk counts one update per gate whose controls match; F_3 on a basis state
+    writes three outputs."""
+    dims = (3, 2, 4, 3, 2)
+    rng = np.random.default_rng(9)
+    circ = C.permutation_circuit(dims, 80, rng)
+    start = (1, 0, 2, 2, 1)
+    dg = list(start)
+    want = 0
+    for g in circ.gates:
+        if all(dg[c] == v for c, v in zip(g.controls, g.cvals)):
+            want += 1
+            dg[g.targets[0]] = (dg[g.targets[0]] + g.a) % dims[g.targets[0]]
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_set_basis(sp, start)
+        for g in circ.gates:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        assert Q.qd_sparse_updates(sp) == want
+        Q.apply_circuit_gate_sparse(sp, C.Gate("F", (0,)), dims)
+        assert Q.qd_sparse_updates(sp) == want + 3
+    finally:
+        Q.qd_sparse_free(sp)
