@@ -388,6 +388,12 @@ int qd_sparse_set_basis(qd_sparse* s, const int32_t* values);
 int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
                          const int32_t* control_values, int32_t m, const double* U, uint32_t flags);
 
+/* Apply count gates in order (qd_gate as for qd_fuse; flags as qd_apply_gate_ex). Every gate is
+ * validated before any device work. Runs of consecutive monomial gates (at most 4 targets and 8
+ * controls each) are applied in one pass over the list with the entry's digits held in LDS; the
+ * result is the same, bit for bit, as gate by gate. */
+int qd_sparse_apply_gates(qd_sparse* s, const qd_gate* gates, int32_t count, uint32_t flags);
+
 /* Number of entries. Synchronises. */
 int qd_sparse_count(qd_sparse* s, int64_t* out);
 

@@ -36,7 +36,8 @@ __all__ = [
     "qd_circuit_create", "qd_circuit_add", "qd_qasm_parse", "qd_circuit_size", "qd_circuit_dims", "qd_circuit_name",
     "qd_circuit_gate", "qd_circuit_gates", "qd_circuit_moments", "qd_circuit_decompose", "qd_circuit_apply",
     "qd_circuit_free", "qd_circuit_apply_sparse",
-    "qd_sparse_init", "qd_sparse_upload", "qd_sparse_set_basis", "qd_sparse_apply_gate", "qd_sparse_count",
+    "qd_sparse_init", "qd_sparse_upload", "qd_sparse_set_basis", "qd_sparse_apply_gate", "qd_sparse_apply_gates",
+    "qd_sparse_count",
     "qd_sparse_download", "qd_sparse_device_lists", "qd_sparse_norm2", "qd_sparse_probabilities",
     "qd_sparse_to_dense", "qd_sparse_updates", "qd_sparse_sync", "qd_sparse_free", "apply_circuit_gate_sparse",
     "qd_batch_create", "qd_batch_size", "qd_batch_offset", "qd_batch_reset",
@@ -136,6 +137,7 @@ _SIGS = {
     "qd_sparse_set_basis": (C.c_int, [_P, _I32P]),
     "qd_sparse_apply_gate": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
     "qd_sparse_count": (C.c_int, [_P, _I64P]),
+    "qd_sparse_apply_gates": (C.c_int, [_P, C.POINTER(_Gate), C.c_int32, C.c_uint32]),
     "qd_sparse_download": (C.c_int, [_P, _P, _P, C.c_int64, _I64P]),
     "qd_sparse_device_lists": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), _I64P]),
     "qd_sparse_norm2": (C.c_int, [_P, _DP]),
@@ -628,6 +630,15 @@ def qd_sparse_apply_gate(sp: int, targets, controls, control_values, U, flags: i
 def apply_circuit_gate_sparse(sp: int, gate, dims, flags: int = 0):
     """qd_sparse_apply_gate for one gate record."""
     qd_sparse_apply_gate(sp, gate.targets, gate.controls, gate.cvals, gate_unitary(gate, dims), flags)
+
+
+def qd_sparse_apply_gates(sp: int, gates, flags: int = 0) -> None:
+    """Gate records applied in order (runs of monomial gates in one pass over the list)."""
+    dims = _SPARSE_DIMS[sp]
+    for g in gates:
+        _check_shape(dims, g.targets, gate_unitary(g, dims))
+    ga = GateArray(gates, lambda i: dims)
+    _check(load().qd_sparse_apply_gates(_P(sp), ga.arr, ga.n, int(flags)))
 
 
 def qd_sparse_count(sp: int) -> int:

@@ -243,6 +243,157 @@ __global__ __launch_bounds__(kBlock) void k_monomial(const int64_t* __restrict__
   wave_count(hits, upd);
 }
 
+// ------------------------------------------------------------------------------------------ fused runs
+// A run of monomial gates applied in one pass: each entry's digits are decoded once into LDS (one
+// byte per qudit), every gate of the run updates them (a shift X_{+a} adds a mod d; a table gate
+// replaces its target digits by those of the row its column maps to and multiplies the amplitude),
+// and the index is encoded and written once. Per entry the operations and their order are those of
+// the gate-by-gate path, so the results are the same bits. The run's gate descriptors and tables
+// (at most kRunStage bytes per launch) are staged in LDS once per workgroup and read by broadcast;
+// workgroups are persistent and walk the list.
+constexpr int kRunK = 4;             // targets per gate in a fused run
+constexpr int kRunM = 8;             // controls per gate in a fused run
+constexpr int kRunMin = 4;           // shorter runs go gate by gate
+constexpr int kRunStage = 8192;      // bytes of descriptors and tables per launch
+constexpr int kRunBlocksPerCU = 8;
+
+struct RunGateC {                    // 32 bytes
+  uint8_t shift, k, m, pad;          // shift > 0: X_{+shift} on one target with unit entries
+  uint8_t tq[kRunK];                 // targets, first most significant
+  uint8_t td1[kRunK];                // their dimensions minus one
+  uint8_t cq[kRunM];                 // controls
+  uint8_t cv[kRunM];                 // control values
+  int32_t tab;                       // first table row of a table gate
+};
+static_assert(sizeof(RunGateC) == 32, "descriptor layout");
+
+struct RunQudit {
+  Magic64 md;                        // division by the qudit's dimension
+  int64_t stride;
+  uint32_t d, pad;
+};
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
+
+// Each thread carries E entries; entry i's digit of qudit q sits at dig[(q * E + i) * kBlock + lane].
+template <bool UNIT, int kRunE>
+__global__ __launch_bounds__(kBlock) void k_mono_run(const int64_t* __restrict__ cnt, int64_t* __restrict__ idx,
+                                                     double2* __restrict__ amp, const uint4* __restrict__ stage,
+                                                     int32_t stage16, int32_t ngates, int32_t o_nd, int32_t o_ph,
+                                                     int32_t o_un, const RunQudit* __restrict__ rq, int32_t nq,
+                                                     int64_t* __restrict__ upd) {
+  extern __shared__ uint4 lds[];
+  for (int i = threadIdx.x; i < stage16; i += kBlock) lds[i] = stage[i];
+  const uint8_t* stg = reinterpret_cast<const uint8_t*>(lds);
+  const uint4* gd = lds;                                               // two uint4 per gate
+  const uint32_t* nd = reinterpret_cast<const uint32_t*>(stg + o_nd);
+  const double2* ph = reinterpret_cast<const double2*>(stg + o_ph);
+  const uint8_t* un = stg + o_un;
+  uint8_t* my = reinterpret_cast<uint8_t*>(lds + stage16) + threadIdx.x;
+  constexpr int QS = kRunE * kBlock;                                   // stride between qudits
+  __syncthreads();
+  const int64_t n = *cnt;
+  int hits = 0;
+  for (int64_t b0 = int64_t(blockIdx.x) * (kRunE * kBlock); b0 < n; b0 += int64_t(gridDim.x) * (kRunE * kBlock)) {
+    int64_t e[kRunE];
+    bool active[kRunE];
+    uint64_t t[kRunE];
+#pragma unroll
+    for (int i = 0; i < kRunE; ++i) {
+      e[i] = b0 + i * kBlock + threadIdx.x;
+      active[i] = e[i] < n;
+      t[i] = active[i] ? uint64_t(__builtin_nontemporal_load(idx + e[i])) : 0;
+    }
+    for (int q = nq - 1; q >= 0; --q) {
+      const RunQudit r = rq[q];
+#pragma unroll
+      for (int i = 0; i < kRunE; ++i) {
+        const uint64_t qt = mdiv(t[i], r.md);
+        my[q * QS + i * kBlock] = uint8_t(t[i] - qt * r.d);
+        t[i] = qt;
+      }
+    }
+    double2 a[kRunE];
+    bool changed[kRunE];
+    int eh[kRunE];
+#pragma unroll
+    for (int i = 0; i < kRunE; ++i) {
+      a[i] = make_double2(0.0, 0.0);
+      if (!UNIT && active[i]) a[i] = amp[e[i]];
+      changed[i] = false;
+      eh[i] = 0;
+    }
+    uint4 A = gd[0], B = gd[1];
+    for (int gi = 0; gi < ngates; ++gi) {
+      const uint4 cA = A, cB = B;
+      if (gi + 1 < ngates) {                                           // next descriptor in flight
+        A = gd[2 * gi + 2];
+        B = gd[2 * gi + 3];
+      }
+      const uint32_t w0 = __builtin_amdgcn_readfirstlane(cA.x);
+      const uint32_t m = byte_of(w0, 2);
+      const uint32_t tqw = __builtin_amdgcn_readfirstlane(cA.y), tdw = __builtin_amdgcn_readfirstlane(cA.z);
+      bool ok[kRunE];
+#pragma unroll
+      for (int i = 0; i < kRunE; ++i) ok[i] = active[i];
+      if (m) {
+        const uint32_t c0 = __builtin_amdgcn_readfirstlane(cA.w), c1 = __builtin_amdgcn_readfirstlane(cB.x);
+        const uint32_t v0 = __builtin_amdgcn_readfirstlane(cB.y), v1 = __builtin_amdgcn_readfirstlane(cB.z);
+        for (uint32_t j = 0; j < m; ++j) {
+          const uint32_t cq = byte_of(j < 4 ? c0 : c1, int(j & 3));
+          const uint32_t cv = byte_of(j < 4 ? v0 : v1, int(j & 3));
+#pragma unroll
+          for (int i = 0; i < kRunE; ++i) ok[i] = ok[i] & (uint32_t(my[cq * QS + i * kBlock]) == cv);
+        }
+      }
+      const uint32_t shift = byte_of(w0, 0);
+      if (shift) {
+        const uint32_t q = byte_of(tqw, 0), d = byte_of(tdw, 0) + 1;
+#pragma unroll
+        for (int i = 0; i < kRunE; ++i) {
+          if (ok[i]) {
+            uint8_t* dq = my + q * QS + i * kBlock;
+            uint32_t v = uint32_t(*dq) + shift;
+            if (v >= d) v -= d;
+            *dq = uint8_t(v);
+            ++eh[i];
+          }
+        }
+      } else {
+        const uint32_t k = byte_of(w0, 1);
+        const int32_t tab = int32_t(__builtin_amdgcn_readfirstlane(cB.w));
+#pragma unroll
+        for (int i = 0; i < kRunE; ++i) {
+          if (ok[i]) {
+            uint32_t loc = 0;
+            for (uint32_t j = 0; j < k; ++j)
+              loc = loc * (byte_of(tdw, int(j)) + 1) + my[byte_of(tqw, int(j)) * QS + i * kBlock];
+            const int32_t ti = tab + int32_t(loc);
+            const uint32_t nw = nd[ti];
+            for (uint32_t j = 0; j < k; ++j) my[byte_of(tqw, int(j)) * QS + i * kBlock] = uint8_t(nw >> (8 * j));
+            if (!UNIT && !un[ti]) {
+              a[i] = cmul(ph[ti], a[i]);
+              changed[i] = true;
+            }
+            ++eh[i];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kRunE; ++i) {
+      if (eh[i]) {
+        uint64_t x = 0;
+        for (int q = 0; q < nq; ++q) x += uint64_t(my[q * QS + i * kBlock]) * uint64_t(rq[q].stride);
+        __builtin_nontemporal_store(int64_t(x), idx + e[i]);
+        if (!UNIT && changed[i]) amp[e[i]] = a[i];
+      }
+      hits += eh[i];
+    }
+  }
+  wave_count(hits, upd);
+}
+
 // ------------------------------------------------------------------------------------------ dense gates
 __global__ __launch_bounds__(kBlock) void k_table_clear(uint64_t* __restrict__ keys, int32_t* __restrict__ first, uint64_t H) {
   const uint64_t h = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -758,39 +909,194 @@ static int apply_dense(qd_sparse* s, const GatePlan& p, const Desc& g) {
   return QD_OK;
 }
 
-// Apply validated gates in order. Consecutive monomial gates share one parameter upload (up to
-// kPackMax bytes), so a permutation network costs one host-to-device copy per run, not per gate.
-constexpr size_t kPackMax = size_t(4) << 20;
+static bool run_eligible(const GatePlan& p) {
+  return p.k <= kRunK && p.m <= kRunM && 64 + 32 + size_t(p.dT) * 21 <= size_t(kRunStage);
+}
 
+// shift a > 0 when the gate is X_{+a} on one target with unit entries, else 0
+static int shift_of(const GatePlan& p, const Register& r) {
+  if (p.k != 1 || p.cls != QD_CLASS_MONOMIAL) return 0;
+  const int d = r.dims[p.targets[0]];
+  const int a = p.dst[0];
+  if (a == 0) return 0;
+  for (int c = 0; c < d; ++c)
+    if (p.dst[size_t(c)] != (c + a) % d || p.ph[2 * size_t(c)] != 1.0 || p.ph[2 * size_t(c) + 1] != 0.0) return 0;
+  return a;
+}
+
+struct RunLaunch {
+  size_t o_stage, o_q;               // staged block and register table in the parameter block
+  int32_t stage16, ng, o_nd, o_ph, o_un;
+  bool all_unit;
+};
+
+// bytes a gate adds to a launch's staged block: its descriptor, and for a table gate d_T rows of
+// packed digits (4 B), phases (16 B) and unit flags (1 B)
+static size_t run_cost(const GatePlan& p, bool shift) { return 32 + (shift ? 0 : size_t(p.dT) * 21); }
+
+// append fused-run launches for plans[b..e) to the parameter block, each staging at most kRunStage bytes
+static void pack_runs(qd_sparse* s, const std::vector<GatePlan>& plans, size_t b, size_t e, Pack& pk,
+                      std::vector<RunLaunch>& out) {
+  const Register& r = s->reg;
+  std::vector<RunQudit> Q(size_t(r.n));
+  for (int q = 0; q < r.n; ++q) {
+    Q[size_t(q)] = RunQudit{};
+    Q[size_t(q)].md = make_magic64(uint64_t(r.dims[q]));
+    Q[size_t(q)].stride = r.strides[q];
+    Q[size_t(q)].d = uint32_t(r.dims[q]);
+  }
+  const size_t o_q = pk.add(Q.data(), Q.size() * sizeof(RunQudit));
+  size_t i = b;
+  while (i < e) {
+    std::vector<RunGateC> G;
+    std::vector<uint32_t> nd;
+    std::vector<double2> ph;
+    std::vector<uint8_t> un;
+    size_t bytes = 64;                 // room for the alignment of three table parts
+    bool all_unit = true;
+    while (i < e) {
+      const GatePlan& p = plans[i];
+      const int sh = shift_of(p, r);
+      const size_t c = run_cost(p, sh > 0);
+      if (!G.empty() && bytes + c > size_t(kRunStage)) break;
+      bytes += c;
+      RunGateC g{};
+      g.shift = uint8_t(sh);
+      g.k = uint8_t(p.k);
+      g.m = uint8_t(p.m);
+      for (int j = 0; j < p.k; ++j) {
+        g.tq[j] = uint8_t(p.targets[j]);
+        g.td1[j] = uint8_t(r.dims[p.targets[j]] - 1);
+      }
+      for (int j = 0; j < p.m; ++j) {
+        g.cq[j] = uint8_t(p.controls[j]);
+        g.cv[j] = uint8_t(p.cvals[j]);
+      }
+      if (sh == 0) {
+        g.tab = int32_t(nd.size());
+        for (int col = 0; col < p.dT; ++col) {
+          int row = p.cls == QD_CLASS_DIAGONAL ? col : p.dst[size_t(col)];
+          uint32_t packed = 0;
+          for (int j = p.k - 1; j >= 0; --j) {
+            const int d = r.dims[p.targets[j]];
+            packed |= uint32_t(row % d) << (8 * j);
+            row /= d;
+          }
+          nd.push_back(packed);
+          const double2 v = make_double2(p.ph[2 * size_t(col)], p.ph[2 * size_t(col) + 1]);
+          ph.push_back(v);
+          const bool u = v.x == 1.0 && v.y == 0.0;
+          un.push_back(uint8_t(u));
+          all_unit = all_unit && u;
+        }
+      }
+      G.push_back(g);
+      ++i;
+    }
+    // staged block: descriptors, packed digits, phases, unit flags (16-byte aligned parts)
+    std::vector<char> blk;
+    auto put = [&](const void* src, size_t n) {
+      const size_t at = (blk.size() + 15) / 16 * 16;
+      blk.resize(at + n);
+      if (n) std::memcpy(blk.data() + at, src, n);
+      return at;
+    };
+    RunLaunch L{};
+    put(G.data(), G.size() * sizeof(RunGateC));
+    L.o_nd = int32_t(put(nd.data(), nd.size() * sizeof(uint32_t)));
+    L.o_ph = int32_t(put(ph.data(), ph.size() * sizeof(double2)));
+    L.o_un = int32_t(put(un.data(), un.size()));
+    blk.resize((blk.size() + 15) / 16 * 16);
+    L.stage16 = int32_t(blk.size() / 16);
+    L.o_stage = pk.add(blk.data(), blk.size());
+    L.o_q = o_q;
+    L.ng = int32_t(G.size());
+    L.all_unit = all_unit;
+    out.push_back(L);
+  }
+}
+
+// E entries per thread (two measured fastest on gfx950: four cost occupancy, one leaves the
+// per-gate descriptor work unshared); LDS = staged block + n x E x 256 digit bytes
+template <int E>
+static void launch_run_e(qd_sparse* s, const RunLaunch& L, char* b, int cus) {
+  const int64_t need = (s->bound + E * kBlock - 1) / (E * kBlock);
+  const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(cus) * kRunBlocksPerCU)));
+  const size_t lds = size_t(L.stage16) * 16 + size_t(s->reg.n) * E * kBlock;
+  const int64_t* cnt = s->misc + kCnt0 + s->cur;
+  auto* st = reinterpret_cast<const uint4*>(b + L.o_stage);
+  auto* Qd = reinterpret_cast<const RunQudit*>(b + L.o_q);
+  if (L.all_unit)
+    hipLaunchKernelGGL((k_mono_run<true, E>), dim3(grid), dim3(kBlock), lds, s->stream, cnt, s->idx[s->cur], s->amp[s->cur],
+                       st, L.stage16, L.ng, L.o_nd, L.o_ph, L.o_un, Qd, int32_t(s->reg.n), s->misc + kUpd);
+  else
+    hipLaunchKernelGGL((k_mono_run<false, E>), dim3(grid), dim3(kBlock), lds, s->stream, cnt, s->idx[s->cur], s->amp[s->cur],
+                       st, L.stage16, L.ng, L.o_nd, L.o_ph, L.o_un, Qd, int32_t(s->reg.n), s->misc + kUpd);
+}
+
+static int launch_run(qd_sparse* s, const RunLaunch& L, char* b) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  }
+  launch_run_e<2>(s, L, b, cus);
+  QD_HIP(hipGetLastError());
+  return QD_OK;
+}
+
+// Apply validated gates in order. A run of consecutive monomial gates shares one parameter upload;
+// stretches of at least kRunMin gates that a fused run can hold go through k_mono_run (one launch
+// per kRunStage bytes of descriptors and tables), the others gate by gate. Dense gates go one by one.
 static int apply_sequence(qd_sparse* s, const SparseGate* gs, size_t count) {
   size_t i = 0;
   while (i < count) {
-    GatePlan p;
-    const SparseGate& g0 = gs[i];
-    make_plan(s->reg, g0.t.data(), int32_t(g0.t.size()), g0.c.data(), g0.v.data(),
-              int32_t(g0.c.size()), g0.U.data(), &p);
-    if (p.cls == QD_CLASS_DENSE) {
-      int rc = apply_dense(s, p, make_desc(s->reg, p));
-      if (rc) return rc;
-      ++i;
-      continue;
-    }
-    Pack pk;
-    std::vector<MonoLaunch> L;
-    L.push_back(pack_monomial(s, p, make_desc(s->reg, p), pk));
-    ++i;
-    while (i < count && pk.buf.size() < kPackMax) {
+    std::vector<GatePlan> plans;
+    while (i < count) {
+      GatePlan p;
       const SparseGate& g = gs[i];
       make_plan(s->reg, g.t.data(), int32_t(g.t.size()), g.c.data(), g.v.data(), int32_t(g.c.size()), g.U.data(), &p);
-      if (p.cls == QD_CLASS_DENSE) break;
-      L.push_back(pack_monomial(s, p, make_desc(s->reg, p), pk));
+      if (p.cls == QD_CLASS_DENSE) {
+        if (plans.empty()) {
+          int rc = apply_dense(s, p, make_desc(s->reg, p));
+          if (rc) return rc;
+          ++i;
+          continue;
+        }
+        break;
+      }
+      plans.push_back(std::move(p));
       ++i;
+    }
+    if (plans.empty()) continue;
+    Pack pk;
+    std::vector<std::pair<int, size_t>> order;   // (0 = single gate, 1 = fused run), launch index
+    std::vector<MonoLaunch> single;
+    std::vector<RunLaunch> runs;
+    size_t j = 0;
+    while (j < plans.size()) {
+      size_t e = j;
+      while (e < plans.size() && run_eligible(plans[e])) ++e;
+      if (e - j >= size_t(kRunMin)) {
+        const size_t r0 = runs.size();
+        pack_runs(s, plans, j, e, pk, runs);
+        for (size_t q = r0; q < runs.size(); ++q) order.emplace_back(1, q);
+        j = e;
+      } else {
+        single.push_back(pack_monomial(s, plans[j], make_desc(s->reg, plans[j]), pk));
+        order.emplace_back(0, single.size() - 1);
+        ++j;
+      }
     }
     void* dev = nullptr;
     int rc = ring_push_stream(&s->ring, s->stream, pk.buf.data(), pk.buf.size(), &dev);
     if (rc) return rc;
-    for (const MonoLaunch& l : L)
-      if ((rc = launch_monomial(s, l, static_cast<char*>(dev)))) return rc;
+    for (const auto& o : order) {
+      rc = o.first ? launch_run(s, runs[o.second], static_cast<char*>(dev))
+                   : launch_monomial(s, single[o.second], static_cast<char*>(dev));
+      if (rc) return rc;
+    }
   }
   return QD_OK;
 }
@@ -928,6 +1234,27 @@ int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const 
   for (int j = 0; j < k; ++j) dT *= s->reg.dims[targets[j]];
   g.U.assign(U, U + 2 * size_t(dT) * size_t(dT));
   return sparse_apply_gates(s, &g, 1, flags);
+}
+
+int qd_sparse_apply_gates(qd_sparse* s, const qd_gate* gates, int32_t count, uint32_t flags) {
+  if (!s || count < 0 || (count > 0 && !gates)) return fail(QD_EINVAL, "null argument or negative count");
+  std::vector<SparseGate> seq(static_cast<size_t>(count));
+  for (int32_t i = 0; i < count; ++i) {
+    const qd_gate& g = gates[i];
+    int rc = validate_gate(s->reg, g.targets, g.k, g.controls, g.control_values, g.m, g.U, flags);
+    if (rc) return rc;
+    SparseGate& q = seq[size_t(i)];
+    q.t.assign(g.targets, g.targets + g.k);
+    if (g.m > 0) {
+      q.c.assign(g.controls, g.controls + g.m);
+      q.v.assign(g.control_values, g.control_values + g.m);
+    }
+    int64_t dT = 1;
+    for (int j = 0; j < g.k; ++j) dT *= s->reg.dims[g.targets[j]];
+    q.U.assign(g.U, g.U + 2 * size_t(dT) * size_t(dT));
+  }
+  // every gate passed the checks above; the second pass only repeats the cheap ones
+  return sparse_apply_gates(s, seq.data(), seq.size(), flags | QD_FLAG_SKIP_UNITARY_CHECK);
 }
 
 int qd_sparse_count(qd_sparse* s, int64_t* out) {

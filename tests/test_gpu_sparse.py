@@ -97,8 +97,17 @@ def test_permutation_walk_on_huge_registers(stream, dims):
     circ = C.permutation_circuit(dims, 300, rng)
     start = tuple(int(rng.integers(0, d)) for d in dims)
     idx, amp = run_sparse(dims, circ.gates, stream, basis=start)
-    assert idx.tolist() == [_flat(dims, _digit_walk(dims, circ.gates, start))]
+    want = [_flat(dims, _digit_walk(dims, circ.gates, start))]
+    assert idx.tolist() == want
     assert amp.tolist() == [1.0 + 0.0j]
+    sp = Q.qd_sparse_init(dims, 0, stream)                   # the same walk as one fused run
+    try:
+        Q.qd_sparse_set_basis(sp, start)
+        Q.qd_sparse_apply_gates(sp, circ.gates)
+        idx, amp = Q.qd_sparse_download(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+    assert idx.tolist() == want and amp.tolist() == [1.0 + 0.0j]
 
 
 def test_lists_grow_from_a_tiny_capacity(stream):
@@ -295,3 +304,101 @@ def test_update_counter(stream):
         assert Q.qd_sparse_updates(sp) == want + 3
     finally:
         Q.qd_sparse_free(sp)
+
+
+def random_monomial(d, rng, phases=True):
+    """Explicit monomial unitary: a random permutation matrix times unit-modulus phases (input data)."""
+    perm = rng.permutation(d)
+    U = np.zeros((d, d), dtype=np.complex128)
+    ph = np.exp(2j * np.pi * rng.random(d)) if phases else np.ones(d)
+    U[perm, np.arange(d)] = ph
+    return U
+
+
+def monomial_mix(dims, count, rng, dense_every=0):
+    """Gates of every monomial form (shifts with 0-3 controls, Z, random phased permutations on one
+    or two targets, diagonals) with a dense F gate every `dense_every` gates."""
+    n = len(dims)
+    out = []
+    for i in range(count):
+        if dense_every and i % dense_every == dense_every - 1:
+            out.append(C.Gate("F", (int(rng.integers(n)),)))
+            continue
+        perm = [int(q) for q in rng.permutation(n)]
+        r = rng.random()
+        m = int(rng.integers(0, 4))
+        if r < 0.5:
+            t = perm[0]
+            cs = perm[1:1 + m]
+            out.append(C.Gate("X", (t,), tuple(cs), tuple(int(rng.integers(dims[c])) for c in cs),
+                              a=int(rng.integers(1, dims[t]))))
+        elif r < 0.65:
+            cs = perm[1:1 + m]
+            out.append(C.Gate("Z", (perm[0],), tuple(cs), tuple(int(rng.integers(dims[c])) for c in cs)))
+        else:
+            k = 1 if r < 0.85 else 2
+            tg = perm[:k]
+            cs = perm[k:k + m]
+            dT = int(np.prod([dims[q] for q in tg]))
+            out.append(C.Gate("U", tuple(tg), tuple(cs), tuple(int(rng.integers(dims[c])) for c in cs),
+                              U=random_monomial(dT, rng, phases=rng.random() < 0.7)))
+    return out
+
+
+@pytest.mark.parametrize("seed,dense_every", [(0, 0), (1, 0), (2, 9), (3, 40)])
+def test_fused_runs_match_the_oracle_and_gate_by_gate(stream, seed, dense_every):
+    rng = np.random.default_rng(500 + seed)
+    dims = tuple(int(x) for x in rng.choice([2, 3, 4, 5], size=9))
+    D = int(np.prod(dims))
+    psi0 = C.random_basis_superposition(D, 300, rng)
+    gates = monomial_mix(dims, 400, rng, dense_every)
+    init = nonzero_entries(psi0)
+    want = S.run_circuit(C.Circuit(dims, gates, init_amps=psi0))
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_upload(sp, *init)
+        Q.qd_sparse_apply_gates(sp, gates)
+        fused = Q.qd_sparse_download(sp)
+        upd_fused = Q.qd_sparse_updates(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_upload(sp, *init)
+        for g in gates:
+            Q.apply_circuit_gate_sparse(sp, g, dims)
+        single = Q.qd_sparse_download(sp)
+        upd_single = Q.qd_sparse_updates(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+    same_list(fused, want)
+    same_list(single, want)
+    assert upd_fused == upd_single
+
+
+def test_long_runs_and_gates_a_run_cannot_hold(stream):
+    """9000 shifts (three launches of at most 4096 gates), a 9-control gate and a 5-target
+    permutation (both applied gate by gate), on a superposition of 64 basis states."""
+    rng = np.random.default_rng(77)
+    dims = (2,) * 10 + (3,) * 2
+    gates = [C.Gate("F", (q,)) for q in range(6)]
+    perm5 = np.zeros((32, 32), dtype=np.complex128)
+    perm5[(np.arange(32) * 7 + 3) % 32, np.arange(32)] = 1.0
+    for i in range(9000):
+        t = int(rng.integers(12))
+        c = int(rng.integers(11))
+        c = c + 1 if c >= t else c
+        gates.append(C.Gate("X", (t,), (c,), (1,), a=int(rng.integers(1, dims[t]))))
+        if i == 3000:
+            gates.append(C.Gate("X", (11,), tuple(range(9)), (0,) * 9, a=1))
+        if i == 6000:
+            gates.append(C.Gate("U", (0, 2, 4, 6, 8), (), (), U=perm5))
+    want = S.run_circuit(C.Circuit(dims, gates))
+    sp = Q.qd_sparse_init(dims, 0, stream)
+    try:
+        Q.qd_sparse_apply_gates(sp, gates)
+        got = Q.qd_sparse_download(sp)
+    finally:
+        Q.qd_sparse_free(sp)
+    assert len(want[0]) == 64
+    same_list(got, want)
