@@ -14,6 +14,7 @@ Two independent forms of the same definition are provided:
 ``oracle.measure`` holds the readout after the gates: shots of a computational-basis measurement,
 per-qudit marginals and the list of states with non-zero probability (ket output).
 ``oracle.sparse`` holds the sparse state (the list of non-zero amplitudes) and its gate updates.
+``oracle.density`` holds density matrices, gates on them and Kraus channels (full matrix products).
 """
 from .qudit import *  # noqa: F401,F403
 from .qudit import __all__  # noqa: F401
