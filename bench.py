@@ -50,9 +50,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip copy ceiling, fused and batched extras")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the --extras legs and print {\"extras\": ...} (for profiling one leg alone); "
+                         "not the benchmark line")
     ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend,sparse",
+    ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend,sparse,density",
                     help="comma list of extras: copy, qft, brick, batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -457,6 +460,107 @@ def bench_sparse_cpu(tn, seconds):
                                         f"NumPy, 1 thread, {dt:.1f} s"}
 
 
+def _noisy_ops(C, dims, ngates, seed, p=1e-3):
+    """A noisy circuit as data: each gate of the random-circuit sampler (one target, at most one
+    control) followed by a depolarizing channel of strength p on its target."""
+    circ = C.random_circuit(dims, ngates, C.seeded_rng(seed), max_targets=1, max_controls=1)
+    ops = []
+    for g in circ.gates:
+        ops.append(("gate", g))
+        ops.append(("chan", g.targets[0], p))
+    return circ, ops
+
+
+def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
+    """Density matrix of 7 qubits + 4 qutrits (D = 10,368, so D^2 = 1.07e8 elements, 1.72 GB in
+    complex128): 60 gates, each followed by a depolarizing channel on its target. A pass reads and
+    writes its active elements (algorithmic bytes 2 x 16 per element)."""
+    import numpy as np
+    import circuits as C
+    st = torch.cuda.current_stream().cuda_stream
+    dims = (2,) * 7 + (3,) * 4
+    D = int(np.prod(dims))
+    circ, ops = _noisy_ops(C, dims, 60, 1008)
+    kraus = {d: Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, d, 1e-3) for d in set(dims)}
+    unit = {id(g): Q.gate_unitary(g, dims) for g in circ.gates}
+    # passes, as the library forms them: one for a channel and for a gate whose embedding on its
+    # targets and controls has d_G <= 3 (dense U) or <= 4 (monomial or diagonal U); two otherwise,
+    # each touching the D^2 / d_c elements whose (row or column) control digits match
+    passes, active = 0, 0
+    for o in ops:
+        if o[0] == "chan":
+            passes += 1
+            active += D * D
+            continue
+        g = o[1]
+        dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
+        dG = dims[g.targets[0]] * dc
+        fused = dG <= (4 if Q.qd_gate_class(unit[id(g)]) != Q.QD_CLASS_DENSE else 3)
+        passes += 1 if fused else 2
+        active += D * D if fused else 2 * (D * D // dc)
+    rho = Q.qd_density_init(dims, Q.QD_C128, st)
+
+    def run():
+        for o in ops:
+            if o[0] == "gate":
+                g = o[1]
+                Q.qd_density_apply_gate(rho, g.targets, g.controls, g.cvals, unit[id(g)])
+            else:
+                Q.qd_density_apply_channel(rho, (o[1],), kraus[dims[o[1]]])
+
+    run()                                              # warm-up
+    e0, e1 = _ev(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tr = Q.qd_density_trace(rho)
+    pur = Q.qd_density_purity(rho)
+    Q.qd_state_free(rho)
+    alg = 2.0 * 16.0 * active
+    out = {"workload": "density matrix, 7 qubits + 4 qutrits (D = 10,368), 60 gates + 60 depolarizing channels",
+           "elements": D * D, "passes": passes, "circuit_ms": ms, "ms_per_pass": ms / passes,
+           "element_updates_per_s": active / (ms * 1e-3), "trace_re": tr.real, "purity": pur,
+           "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}}
+    if cpu:
+        out["cpu_oracle"] = bench_density_cpu(C, cpu_seconds)
+    return out
+
+
+def bench_density_cpu(C, seconds):
+    """The density oracle (never tuned; full operators and matrix products) on a bounded sample of the
+    same workload: the same noisy-circuit recipe on 3 qubits + 2 qutrits (D = 72)."""
+    import numpy as np
+    import oracle as O
+    from oracle import density as Dm
+    from threadpoolctl import threadpool_limits
+    dims = (2,) * 3 + (3,) * 2
+    D = int(np.prod(dims))
+    circ, ops = _noisy_ops(C, dims, 60, 1008)
+    rho = Dm.from_state(O.basis_state(dims))
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            for o in ops:
+                if o[0] == "gate":
+                    g = o[1]
+                    rho = Dm.apply_unitary(rho, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+                else:
+                    rho = Dm.apply_channel(rho, dims, (o[1],), Dm.depolarizing(dims[o[1]], 1e-3))
+                done += 1
+                if time.perf_counter() - t0 >= seconds:
+                    break
+        dt = time.perf_counter() - t0
+    return {"value": done * D * D / dt, "unit": "element updates/s (one operation over all D^2 elements)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{done} operations of the same recipe on 3 qubits + 2 qutrits (D = {D}), NumPy, 1 thread, {dt:.1f} s"}
+
+
 def bench_batch(Q, torch, ncirc=4096):
     """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
     layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
@@ -574,11 +678,12 @@ def main():
         Q.qd_state_free(scratch)
         tuning = open(path).read().replace("\n", "")
         log(f"autotuned: {tuning}")
-    log(f"plain complex128: D={circ.D} gates={len(circ.gates)} steps={args.steps} warmup={args.warmup}")
-    plain = bench_plain(args, Q, torch, circ)
-    plain["roofline"]["traffic"] = measured_traffic(plain["roofline"]["kernel"])
-    log(f"plain: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} amp-upd/s, "
-        f"dominant {plain['roofline']['kernel']} {plain['roofline']['achieved']:.0f} GB/s")
+    if not args.extras_only:
+        log(f"plain complex128: D={circ.D} gates={len(circ.gates)} steps={args.steps} warmup={args.warmup}")
+        plain = bench_plain(args, Q, torch, circ)
+        plain["roofline"]["traffic"] = measured_traffic(plain["roofline"]["kernel"])
+        log(f"plain: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} amp-upd/s, "
+            f"dominant {plain['roofline']['kernel']} {plain['roofline']['achieved']:.0f} GB/s")
     extras = {}
     which = set() if args.no_extras else set(args.extras.split(","))
     if "copy" in which:
@@ -610,8 +715,17 @@ def main():
             f"({b['gate_entry_steps_per_s']:.3e} gate-entry steps/s, {b['roofline']['achieved']:.2f} Tops/s alg. = "
             f"{100 * b['roofline']['frac']:.0f}% of the integer issue rate), "
             f"x{sp['vs_dense']['speedup_vs_dense']:.0f} vs dense c128 on the 2^16-entry network")
+    if "density" in which:
+        dn = bench_density(Q, torch, cpu=not args.no_cpu, cpu_seconds=min(args.cpu_seconds, 10.0))
+        extras["density_noisy_circuit"] = dn
+        log(f"density: {dn['passes']} passes over {dn['elements']} elements in {dn['circuit_ms']:.1f} ms "
+            f"({dn['ms_per_pass']:.3f} ms/pass, {dn['roofline']['achieved']:.0f} GB/s = "
+            f"{100 * dn['roofline']['frac']:.0f}% of HBM peak), trace {dn['trace_re']:.12f}")
     if tuning:
         extras["tuning"] = tuning
+    if args.extras_only:
+        print(json.dumps({"extras": extras}), flush=True)
+        return
     out = {
         "metric": METRIC,
         "value": plain["value"],

@@ -431,6 +431,64 @@ int qd_circuit_apply_sparse(qd_sparse* s, const qd_circuit* c);
 
 void qd_sparse_free(qd_sparse* s);
 
+/* ---------------------------------------------------------------- density matrices and noise (Sec. 3.1, 3.3, 7) */
+
+/* The paper keeps states as vectors and names density matrices (Sec. 3.3) and noise models (Sec. 7)
+ * as the next representations; a channel on qudits of dimensions (d_1..d_k) has Kraus matrices of
+ * the size a gate on them has (Sec. 3.1). A density matrix rho over n qudits (D = prod d_i) is a
+ * qd_state over the doubled register dims ++ dims: row qudits 0..n-1, column qudits n..2n-1,
+ * element (x, y) at flat index x * D + y. qd_norm2, qd_state_download and the other state calls
+ * see that doubled register. */
+
+/* rho = |0..0><0..0| over dims[0..n-1] (1 <= n <= 32); prec QD_C128 or QD_C64. */
+int qd_density_init(const int32_t* dims, int32_t n, int32_t prec, void* hip_stream, qd_state** out);
+
+/* rho = psi psi^dagger for a pure state of the same register and precision. QD_EDIM / QD_EINVAL
+ * otherwise. Asynchronous on rho's stream (psi's stream is drained first). */
+int qd_density_from_state(qd_state* rho, const qd_state* psi);
+
+/* rho -> G rho G^dagger for the (controlled) gate of qd_apply_gate_ex on the physical register
+ * (targets and controls are 0..n-1; validation and flags as there). With G embedded on its targets
+ * and controls (d_G = d_T x prod d_c), a gate with d_G <= 3, or d_G <= 4 when U is monomial or
+ * diagonal, is one pass of G (x) conj(G) on (T, C, T + n, C + n); others are two passes (U on T,
+ * conj(U) on T + n with controls c + n). Asynchronous. */
+int qd_density_apply_gate(qd_state* rho, const int32_t* targets, int32_t k, const int32_t* controls,
+                          const int32_t* control_values, int32_t m, const double* U, uint32_t flags);
+
+/* rho -> sum_k K_k rho K_k^dagger for nk Kraus operators on targets (d_T <= 32), given as nk
+ * consecutive d_T x d_T row-major interleaved complex matrices (first target most significant).
+ * QD_ENOTUNITARY unless max |sum_k K_k^dagger K_k - I| <= 1e-10 (QD_FLAG_SKIP_UNITARY_CHECK skips
+ * the test). Applied as one pass of sum_k K_k (x) conj(K_k) on (T, T + n). Asynchronous. */
+int qd_density_apply_channel(qd_state* rho, const int32_t* targets, int32_t k, const double* kraus, int32_t nk,
+                             uint32_t flags);
+
+/* Named one-qudit channels (readings; the paper defines none):
+ *  QD_CHANNEL_DEPOLARIZING   rho -> (1 - p) rho + p tr(rho) I/d: sqrt(1 - p + p/d^2) I and
+ *                            sqrt(p/d^2) X^a Z^b, (a, b) != (0, 0), operator a d + b (d^2 of them);
+ *  QD_CHANNEL_DEPHASING      sqrt(1 - p) I and sqrt(p/(d-1)) Z^b, b = 1..d-1 (d of them);
+ *  QD_CHANNEL_AMPLITUDE_DAMPING  K_0 = |0><0| + sqrt(1 - p) sum_{j>=1} |j><j|, K_j = sqrt(p) |j-1><j|
+ *                            (d of them).
+ * X and Z are the generalized shift and phase gates (Sec. 2.1). *nk receives the count; with out
+ * != NULL and cap >= count the operators are written as for qd_density_apply_channel. Host only. */
+enum { QD_CHANNEL_DEPOLARIZING = 0, QD_CHANNEL_DEPHASING = 1, QD_CHANNEL_AMPLITUDE_DAMPING = 2 };
+int qd_channel_kraus(int32_t kind, int32_t d, double p, double* out, int32_t cap, int32_t* nk);
+
+/* tr(rho) (both parts), fixed reduction order. Synchronises. */
+int qd_density_trace(qd_state* rho, double* re, double* im);
+
+/* Re rho[x, x] for x = 0..D-1 (the outcome distribution) into out (device memory when
+ * out_is_device). Synchronises. */
+int qd_density_probabilities(qd_state* rho, double* out, int32_t out_is_device);
+
+/* tr(rho^2) = sum |rho_xy|^2 (rho Hermitian). Synchronises. */
+int qd_density_purity(qd_state* rho, double* out);
+
+/* <psi|rho|psi> (the fidelity with a pure state of the same register and precision). Synchronises. */
+int qd_density_fidelity(qd_state* rho, const qd_state* psi, double* out);
+
+/* Number of physical qudits n (0 for a pure state). */
+int qd_density_size(const qd_state* rho, int32_t* n_qudits);
+
 /* ---------------------------------------------------------------- batched circuits (Sec. 3.5) */
 
 /* nc independent registers in one device arena: circuit c has n_per[c] qudits whose dims follow

@@ -22,6 +22,10 @@ __all__ = [
     "QD_C128", "QD_C64", "QD_MODE_FP64_PLAIN", "QD_MODE_FP32_MFMA", "QD_MODE_BF16X3_MFMA",
     "QD_FLAG_SKIP_UNITARY_CHECK", "QD_GATE_X", "QD_GATE_Z", "QD_GATE_F", "QD_GATE_I",
     "QD_CLASS_DENSE", "QD_CLASS_MONOMIAL", "QD_CLASS_DIAGONAL",
+    "QD_CHANNEL_DEPOLARIZING", "QD_CHANNEL_DEPHASING", "QD_CHANNEL_AMPLITUDE_DAMPING",
+    "qd_density_init", "qd_density_from_state", "qd_density_apply_gate", "qd_density_apply_channel",
+    "qd_channel_kraus", "qd_density_trace", "qd_density_probabilities", "qd_density_purity",
+    "qd_density_fidelity", "qd_density_size", "qd_density_dims", "apply_circuit_gate_density",
     "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
     "QD_TUNE_BATCH_GRID",
@@ -53,6 +57,7 @@ QD_MODE_FP64_PLAIN, QD_MODE_FP32_MFMA, QD_MODE_BF16X3_MFMA = 0, 1, 2
 QD_FLAG_SKIP_UNITARY_CHECK = 1
 QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
 QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2
+QD_CHANNEL_DEPOLARIZING, QD_CHANNEL_DEPHASING, QD_CHANNEL_AMPLITUDE_DAMPING = 0, 1, 2
 QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
  QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID) = range(10)
@@ -145,6 +150,16 @@ _SIGS = {
     "qd_sparse_to_dense": (C.c_int, [_P, _P]),
     "qd_sparse_sync": (C.c_int, [_P]),
     "qd_sparse_updates": (C.c_int, [_P, _I64P]),
+    "qd_density_init": (C.c_int, [_I32P, C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "qd_density_from_state": (C.c_int, [_P, _P]),
+    "qd_density_apply_gate": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
+    "qd_density_apply_channel": (C.c_int, [_P, _I32P, C.c_int32, _DP, C.c_int32, C.c_uint32]),
+    "qd_channel_kraus": (C.c_int, [C.c_int32, C.c_int32, C.c_double, _DP, C.c_int32, _I32P]),
+    "qd_density_trace": (C.c_int, [_P, _DP, _DP]),
+    "qd_density_probabilities": (C.c_int, [_P, _DP, C.c_int32]),
+    "qd_density_purity": (C.c_int, [_P, _DP]),
+    "qd_density_fidelity": (C.c_int, [_P, _P, _DP]),
+    "qd_density_size": (C.c_int, [_P, _I32P]),
     "qd_sparse_free": (None, [_P]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
@@ -595,6 +610,83 @@ def qd_circuit_free(c: int) -> None:
 
 def qd_circuit_apply_sparse(sp: int, c: int) -> None:
     _check(load().qd_circuit_apply_sparse(_P(sp), _P(c)))
+
+
+# ------------------------------------------------------------------------------ density matrices
+def qd_density_init(dims, prec: int = QD_C128, stream: int = 0) -> int:
+    out = _P()
+    _check(load().qd_density_init(_i32(dims), len(dims), int(prec), _P(stream), C.byref(out)))
+    return out.value
+
+
+def qd_density_size(rho: int) -> int:
+    n = C.c_int32()
+    _check(load().qd_density_size(_P(rho), C.byref(n)))
+    return int(n.value)
+
+
+def qd_density_dims(rho: int):
+    """The physical register (the first half of the doubled one)."""
+    return qd_state_dims(rho)[:qd_density_size(rho)]
+
+
+def qd_density_from_state(rho: int, psi: int) -> None:
+    _check(load().qd_density_from_state(_P(rho), _P(psi)))
+
+
+def qd_density_apply_gate(rho: int, targets, controls, control_values, U, flags: int = 0) -> None:
+    Uc = _cplx(U)
+    _check_shape(qd_density_dims(rho), targets, Uc)
+    _check(load().qd_density_apply_gate(_P(rho), _i32(targets), len(targets), _i32(controls), _i32(control_values),
+                                        len(controls), _dptr(Uc), int(flags)))
+
+
+def apply_circuit_gate_density(rho: int, gate, dims, flags: int = 0):
+    """qd_density_apply_gate for one gate record."""
+    qd_density_apply_gate(rho, gate.targets, gate.controls, gate.cvals, gate_unitary(gate, dims), flags)
+
+
+def qd_density_apply_channel(rho: int, targets, kraus, flags: int = 0) -> None:
+    """Kraus operators (a list of d_T x d_T arrays) on the targets."""
+    ks = [_cplx(K) for K in kraus]
+    for K in ks:
+        _check_shape(qd_density_dims(rho), targets, K)
+    flat = np.ascontiguousarray(np.concatenate([K.reshape(-1) for K in ks])) if ks else np.zeros(1, np.complex128)
+    _check(load().qd_density_apply_channel(_P(rho), _i32(targets), len(targets), _dptr(flat), len(ks), int(flags)))
+
+
+def qd_channel_kraus(kind: int, d: int, p: float) -> list:
+    """The library's Kraus operators of a named one-qudit channel."""
+    nk = C.c_int32()
+    _check(load().qd_channel_kraus(int(kind), int(d), float(p), None, 0, C.byref(nk)))
+    out = np.zeros(nk.value * d * d, dtype=np.complex128)
+    _check(load().qd_channel_kraus(int(kind), int(d), float(p), _dptr(out), nk.value, C.byref(nk)))
+    return [out[i * d * d:(i + 1) * d * d].reshape(d, d).copy() for i in range(nk.value)]
+
+
+def qd_density_trace(rho: int) -> complex:
+    re, im = C.c_double(), C.c_double()
+    _check(load().qd_density_trace(_P(rho), C.byref(re), C.byref(im)))
+    return complex(re.value, im.value)
+
+
+def qd_density_probabilities(rho: int) -> np.ndarray:
+    D = int(np.prod(qd_density_dims(rho)))
+    out = np.empty(D, dtype=np.float64)
+    _check(load().qd_density_probabilities(_P(rho), _dptr(out), 0))
+    return out
+
+
+def qd_density_purity(rho: int) -> float:
+    v = C.c_double()
+    _check(load().qd_density_purity(_P(rho), C.byref(v)))
+    return float(v.value)
+
+
+def qd_density_fidelity(rho: int, psi: int) -> float:
+    v = C.c_double()
+    _check(load().qd_density_fidelity(_P(rho), _P(psi), C.byref(v)))
+    return float(v.value)
 
 
 # ------------------------------------------------------------------------------ sparse state

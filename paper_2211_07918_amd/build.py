@@ -28,7 +28,8 @@ CXXFLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["qd_runtime.cpp", "qd_gates.hip", "qd_reduce.hip", "qd_fuse.hip", "qd_mfma.hip", "qd_batch.hip",
-           "qd_tune.cpp", "qd_measure.hip", "qd_frontend.cpp", "qd_sparse.hip"]
+           "qd_tune.cpp", "qd_measure.hip", "qd_frontend.cpp", "qd_sparse.hip",
+           "qd_density.hip"]
 
 
 def _hipcc() -> str:

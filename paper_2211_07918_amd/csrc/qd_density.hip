@@ -1,0 +1,458 @@
+// Density matrices and noise channels. The paper keeps states as vectors and names density
+// matrices (Sec. 3.3) and noise models (Sec. 7) as the next representations; a channel on qudits
+// of dimensions (d_1..d_k) has Kraus matrices of the size a gate on them has (Sec. 3.1).
+//
+// A density matrix rho over a register of n qudits (D = prod d_i) is stored as a state over the
+// doubled register dims ++ dims: row qudits 0..n-1, column qudits n..2n-1, so element (x, y) sits
+// at flat index x * D + y (row-major). With this layout
+//   * a gate G maps rho -> G rho G^dagger, i.e. G on the row qudits and conj(G) on the column
+//     qudits. With G embedded on its targets and controls (dimension d_G = d_T x d_C), a gate with
+//     d_G <= kFuseGate (dense U) or d_G <= kFuseMono (monomial or diagonal U) is one pass of
+//     G (x) conj(G) over (T, C, T + n, C + n); other gates take two passes (U on T with its
+//     controls, conj(U) on T + n with the shifted controls);
+//   * a channel with Kraus operators K_1..K_r maps rho -> sum_k K_k rho K_k^dagger, one pass of the
+//     superoperator S = sum_k K_k (x) conj(K_k) over (T, T + n).
+// Both run through the library's gate kernels (HBM-bound passes over the D^2 elements). The
+// readouts here (outer product, diagonal, trace, <psi|rho|psi>) are HBM-bound kernels of their own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "qd_internal.h"
+#include "qd_stream.h"
+
+namespace qd {
+namespace dm {
+
+constexpr int kBlock = 256;
+// d_G (targets x controls) up to which a gate is one pass of G (x) conj(G): the superoperator must
+// stay on the fast gate kernels (dense up to 9 x 9, monomial up to 16 x 16; larger ones take the
+// generic kernel, which measured slower than two passes)
+constexpr int kFuseGate = 3;          // dense U
+constexpr int kFuseMono = 4;          // monomial or diagonal U
+constexpr int kMaxChannelDim = 32;    // d_T of a channel (its superoperator is d_T^2 x d_T^2 <= 1024)
+constexpr int kRedGrid = 1024;
+
+template <typename R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
+
+// rho[x, y] = psi[x] conj(psi[y]); one column index y per thread, rows x strided over grid.y
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_outer(const R* __restrict__ psi_raw, R* __restrict__ rho_raw, uint64_t D) {
+  using C = typename Cx<R>::T;
+  const C* psi = reinterpret_cast<const C*>(psi_raw);
+  C* rho = reinterpret_cast<C*>(rho_raw);
+  const uint64_t y = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (y >= D) return;
+  const C b = psi[y];
+  const double br = double(b.x), bi = -double(b.y);
+  for (uint64_t x = blockIdx.y; x < D; x += gridDim.y) {
+    const C a = psi[x];
+    const double ar = double(a.x), ai = double(a.y);
+    C v;
+    v.x = R(ar * br - ai * bi);
+    v.y = R(ar * bi + ai * br);
+    st_stream(rho + x * D + y, v);
+  }
+}
+
+// out[x] = Re rho[x, x]
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag(const R* __restrict__ rho_raw, uint64_t D, double* __restrict__ out) {
+  using C = typename Cx<R>::T;
+  const C* rho = reinterpret_cast<const C*>(rho_raw);
+  const uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (x < D) out[x] = double(rho[x * (D + 1)].x);
+}
+
+// fixed-order block sum of NV values per thread into part[blockIdx.x * NV + q]
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* part) {
+  __shared__ double sh[NV][kBlock];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) part[blockIdx.x * NV + q] = sh[q][0];
+}
+
+// trace: partial sums of the diagonal (re, im) over a fixed grid
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_trace_part(const R* __restrict__ rho_raw, uint64_t D, double* __restrict__ part) {
+  using C = typename Cx<R>::T;
+  const C* rho = reinterpret_cast<const C*>(rho_raw);
+  double v[2] = {0.0, 0.0};
+  for (uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x; x < D; x += uint64_t(gridDim.x) * kBlock) {
+    const C a = rho[x * (D + 1)];
+    v[0] += double(a.x);
+    v[1] += double(a.y);
+  }
+  block_sum<2>(v, part);
+}
+
+// <psi|rho|psi> = sum_x conj(psi_x) sum_y rho_xy psi_y: each workgroup takes whole rows (row x of
+// workgroup b: x = b, b + grid, ...), its threads stride over y with coalesced streaming reads
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fidelity_part(const R* __restrict__ rho_raw, const R* __restrict__ psi_raw,
+                                                          uint64_t D, double* __restrict__ part) {
+  using C = typename Cx<R>::T;
+  const C* rho = reinterpret_cast<const C*>(rho_raw);
+  const C* psi = reinterpret_cast<const C*>(psi_raw);
+  double v[2] = {0.0, 0.0};
+  for (uint64_t x = blockIdx.x; x < D; x += gridDim.x) {
+    double rr = 0.0, ri = 0.0;
+    const C* row = rho + x * D;
+    for (uint64_t y = threadIdx.x; y < D; y += kBlock) {
+      const C a = ld_stream(row + y);
+      const C b = psi[y];
+      rr += double(a.x) * double(b.x) - double(a.y) * double(b.y);
+      ri += double(a.x) * double(b.y) + double(a.y) * double(b.x);
+    }
+    const C p = psi[x];
+    // conj(psi_x) * (rr + i ri)
+    v[0] += double(p.x) * rr + double(p.y) * ri;
+    v[1] += double(p.x) * ri - double(p.y) * rr;
+  }
+  block_sum<2>(v, part);
+}
+
+static unsigned red_grid(uint64_t D) {
+  return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(kRedGrid, (D + kBlock - 1) / kBlock)));
+}
+
+// sum the NV partials of g workgroups on the host in a fixed order
+static int finish(qd_state* s, double* part, unsigned g, int nv, double* out) {
+  std::vector<double> h(size_t(g) * nv);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return hip_fail(e, "density reduction");
+  for (int q = 0; q < nv; ++q) {
+    double acc = 0.0;
+    for (unsigned b = 0; b < g; ++b) acc += h[size_t(b) * nv + q];
+    out[q] = acc;
+  }
+  return QD_OK;
+}
+
+static bool same_register(const qd_state* rho, const qd_state* psi) {
+  const int n = rho->dens_n;
+  if (psi->dens_n || psi->reg.n != n) return false;
+  for (int i = 0; i < n; ++i)
+    if (psi->reg.dims[i] != rho->reg.dims[i]) return false;
+  return true;
+}
+
+// validated channel: the superoperator S = sum_k K_k (x) conj(K_k), (d_T^2 x d_T^2, interleaved)
+static std::vector<double> superoperator(const double* kraus, int32_t nk, int dT) {
+  const int N = dT * dT;
+  std::vector<double> S(2 * size_t(N) * N, 0.0);
+  for (int k = 0; k < nk; ++k) {
+    const double* K = kraus + 2 * size_t(k) * dT * dT;
+    for (int a = 0; a < dT; ++a)
+      for (int b = 0; b < dT; ++b)
+        for (int c = 0; c < dT; ++c)
+          for (int d = 0; d < dT; ++d) {
+            // row (a, b), column (c, d): K[a][c] * conj(K[b][d])
+            const double xr = K[2 * (a * dT + c)], xi = K[2 * (a * dT + c) + 1];
+            const double yr = K[2 * (b * dT + d)], yi = -K[2 * (b * dT + d) + 1];
+            const size_t o = 2 * (size_t(a * dT + b) * N + size_t(c * dT + d));
+            S[o] += xr * yr - xi * yi;
+            S[o + 1] += xr * yi + xi * yr;
+          }
+  }
+  return S;
+}
+
+}  // namespace dm
+}  // namespace qd
+
+using namespace qd;
+using namespace qd::dm;
+
+extern "C" {
+
+int qd_density_init(const int32_t* dims, int32_t n, int32_t prec, void* hip_stream, qd_state** out) {
+  if (!dims || !out) return fail(QD_EINVAL, "null argument");
+  if (n < 1 || 2 * n > QD_MAX_QUDITS) return fail(QD_EINVAL, "a density matrix holds 1..32 qudits");
+  std::vector<int32_t> d2(dims, dims + n);
+  d2.insert(d2.end(), dims, dims + n);
+  int rc = qd_state_init(d2.data(), 2 * n, prec, hip_stream, out);   // |0..0><0..0|: element 0 is 1
+  if (rc) return rc;
+  (*out)->dens_n = n;
+  return QD_OK;
+}
+
+int qd_density_from_state(qd_state* rho, const qd_state* psi) {
+  if (!rho || !psi) return fail(QD_EINVAL, "null argument");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  if (!same_register(rho, psi)) return fail(QD_EDIM, "the state's register differs from the density matrix's");
+  if (psi->prec != rho->prec) return fail(QD_EINVAL, "the state and the density matrix differ in precision");
+  const uint64_t D = uint64_t(psi->reg.D);
+  // psi may be written on its own stream: finish it before this stream reads it
+  QD_HIP(hipStreamSynchronize(psi->stream));
+  const dim3 grid(unsigned((D + kBlock - 1) / kBlock), unsigned(std::min<uint64_t>(D, 65535)));
+  if (rho->prec == QD_C128)
+    hipLaunchKernelGGL(k_outer<double>, grid, dim3(kBlock), 0, rho->stream, (const double*)psi->data, (double*)rho->data, D);
+  else
+    hipLaunchKernelGGL(k_outer<float>, grid, dim3(kBlock), 0, rho->stream, (const float*)psi->data, (float*)rho->data, D);
+  QD_HIP(hipGetLastError());
+  return QD_OK;
+}
+
+int qd_density_apply_gate(qd_state* rho, const int32_t* targets, int32_t k, const int32_t* controls,
+                          const int32_t* control_values, int32_t m, const double* U, uint32_t flags) {
+  if (!rho) return fail(QD_EINVAL, "null state");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  const int n = rho->dens_n;
+  // validate against the physical register (targets and controls must be row qudits)
+  Register phys{};
+  int rc = make_register(rho->reg.dims, n, &phys);
+  if (rc) return rc;
+  rc = validate_gate(phys, targets, k, controls, control_values, m, U, flags);
+  if (rc) return rc;
+  int dT = 1;
+  for (int j = 0; j < k; ++j) dT *= phys.dims[targets[j]];
+  int dC = 1;
+  for (int j = 0; j < m; ++j) dC *= phys.dims[controls[j]];
+  const int dG = dT * dC;                 // the gate embedded on (targets, controls)
+  const uint32_t skip = flags | QD_FLAG_SKIP_UNITARY_CHECK;
+  const bool mono = classify(U, dT) != QD_CLASS_DENSE;
+  if ((mono && dG <= kFuseMono) || (!mono && dG <= kFuseGate)) {
+    // one pass of G (x) conj(G) over (T, C, T + n, C + n), G[(t, c), (t', c')] = delta(c, c') times
+    // U[t][t'] when the control digits c hold the control values, else delta(t, t')
+    std::vector<double> G(2 * size_t(dG) * dG, 0.0);
+    int vidx = 0;                          // local index of the control values (first control most significant)
+    for (int j = 0; j < m; ++j) vidx = vidx * phys.dims[controls[j]] + control_values[j];
+    for (int c = 0; c < dC; ++c)
+      for (int t = 0; t < dT; ++t)
+        for (int t1 = 0; t1 < dT; ++t1) {
+          const size_t o = 2 * (size_t(t * dC + c) * dG + size_t(t1 * dC + c));
+          if (c == vidx) {
+            G[o] = U[2 * (t * dT + t1)];
+            G[o + 1] = U[2 * (t * dT + t1) + 1];
+          } else if (t == t1) {
+            G[o] = 1.0;
+          }
+        }
+    const int N = dG * dG;
+    std::vector<double> M(2 * size_t(N) * N);
+    for (int a = 0; a < dG; ++a)
+      for (int b = 0; b < dG; ++b)
+        for (int c = 0; c < dG; ++c)
+          for (int d = 0; d < dG; ++d) {
+            // element ((a, b), (c, d)) = G[a][c] conj(G[b][d])
+            const double xr = G[2 * (a * dG + c)], xi = G[2 * (a * dG + c) + 1];
+            const double yr = G[2 * (b * dG + d)], yi = -G[2 * (b * dG + d) + 1];
+            const size_t o = 2 * (size_t(a * dG + b) * N + size_t(c * dG + d));
+            M[o] = xr * yr - xi * yi;
+            M[o + 1] = xr * yi + xi * yr;
+          }
+    std::vector<int32_t> q(targets, targets + k);
+    q.insert(q.end(), controls, controls + m);
+    for (int j = 0; j < k + m; ++j) q.push_back(q[size_t(j)] + n);
+    return qd_apply_gate_ex(rho, q.data(), 2 * (k + m), nullptr, nullptr, 0, M.data(), skip);
+  }
+  std::vector<int32_t> t2(targets, targets + k), c2;
+  for (int j = 0; j < k; ++j) t2.push_back(targets[j] + n);
+  rc = qd_apply_gate_ex(rho, targets, k, controls, control_values, m, U, skip);
+  if (rc) return rc;
+  std::vector<double> Uc(U, U + 2 * size_t(dT) * dT);
+  for (size_t i = 1; i < Uc.size(); i += 2) Uc[i] = -Uc[i];
+  for (int j = 0; j < m; ++j) c2.push_back(controls[j] + n);
+  return qd_apply_gate_ex(rho, t2.data() + k, k, m ? c2.data() : nullptr, control_values, m, Uc.data(), skip);
+}
+
+int qd_density_apply_channel(qd_state* rho, const int32_t* targets, int32_t k, const double* kraus, int32_t nk,
+                             uint32_t flags) {
+  if (!rho) return fail(QD_EINVAL, "null state");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  if (!kraus || nk < 1) return fail(QD_EINVAL, "a channel needs at least one Kraus operator");
+  const int n = rho->dens_n;
+  Register phys{};
+  int rc = make_register(rho->reg.dims, n, &phys);
+  if (rc) return rc;
+  if (!targets || k < 1 || k > n) return fail(QD_EINVAL, "bad target list");
+  bool used[QD_MAX_QUDITS] = {};
+  int dT = 1;
+  for (int j = 0; j < k; ++j) {
+    if (targets[j] < 0 || targets[j] >= n) return fail(QD_EINVAL, "target out of range");
+    if (used[targets[j]]) return fail(QD_EINVAL, "duplicate target");
+    used[targets[j]] = true;
+    dT *= phys.dims[targets[j]];
+    if (dT > kMaxChannelDim) return fail(QD_EDIM, "channel dimension d_T exceeds 32");
+  }
+  const size_t kk = size_t(dT) * dT;
+  for (size_t i = 0; i < 2 * kk * size_t(nk); ++i)
+    if (!std::isfinite(kraus[i])) return fail(QD_ENOTUNITARY, "a Kraus operator has a NaN or Inf entry");
+  if (!(flags & QD_FLAG_SKIP_UNITARY_CHECK)) {
+    // trace preservation: max |sum_k K_k^dagger K_k - I| <= 1e-10
+    for (int i = 0; i < dT; ++i)
+      for (int j = 0; j < dT; ++j) {
+        double re = 0.0, im = 0.0;
+        for (int q = 0; q < nk; ++q) {
+          const double* K = kraus + 2 * kk * size_t(q);
+          for (int l = 0; l < dT; ++l) {
+            const double ar = K[2 * (l * dT + i)], ai = -K[2 * (l * dT + i) + 1];
+            const double br = K[2 * (l * dT + j)], bi = K[2 * (l * dT + j) + 1];
+            re += ar * br - ai * bi;
+            im += ar * bi + ai * br;
+          }
+        }
+        if (i == j) re -= 1.0;
+        if (std::sqrt(re * re + im * im) > 1e-10) return fail(QD_ENOTUNITARY, "Kraus operators do not sum to the identity");
+      }
+  }
+  std::vector<int32_t> t2(targets, targets + k);
+  for (int j = 0; j < k; ++j) t2.push_back(targets[j] + n);
+  const std::vector<double> S = superoperator(kraus, nk, dT);
+  return qd_apply_gate_ex(rho, t2.data(), 2 * k, nullptr, nullptr, 0, S.data(), QD_FLAG_SKIP_UNITARY_CHECK);
+}
+
+int qd_channel_kraus(int32_t kind, int32_t d, double p, double* out, int32_t cap, int32_t* nk) {
+  if (!nk) return fail(QD_EINVAL, "null count");
+  if (d < 2 || d > QD_MAX_RADIX) return fail(QD_EDIM, "dimension must be 2..256");
+  if (!(p >= 0.0 && p <= 1.0)) return fail(QD_EINVAL, "probability must be in [0, 1]");
+  const int count = kind == QD_CHANNEL_DEPOLARIZING ? d * d : kind == QD_CHANNEL_DEPHASING || kind == QD_CHANNEL_AMPLITUDE_DAMPING ? d : -1;
+  if (count < 0) return fail(QD_EINVAL, "unknown channel kind");
+  *nk = count;
+  if (!out) return QD_OK;
+  if (cap < count) return fail(QD_EINVAL, "output holds fewer Kraus operators than the channel has");
+  const size_t dd = size_t(d) * d;
+  std::fill(out, out + 2 * dd * size_t(count), 0.0);
+  auto at = [&](int q, int r, int c) { return out + 2 * (dd * size_t(q) + size_t(r) * d + c); };
+  std::vector<double> Z(2 * dd), X(2 * dd);
+  if (kind == QD_CHANNEL_AMPLITUDE_DAMPING) {
+    at(0, 0, 0)[0] = 1.0;
+    for (int j = 1; j < d; ++j) {
+      at(0, j, j)[0] = std::sqrt(1.0 - p);
+      at(j, j - 1, j)[0] = std::sqrt(p);
+    }
+    return QD_OK;
+  }
+  // Z^b: diag omega^{b j}, X^a: |j> -> |j + a mod d>, built from the library's named gates
+  int rc = qd_gate_matrix(QD_GATE_Z, d, 0, Z.data());
+  if (rc) return rc;
+  if (kind == QD_CHANNEL_DEPHASING) {
+    for (int b = 0; b < d; ++b) {
+      const double w = b == 0 ? std::sqrt(1.0 - p) : std::sqrt(p / (d - 1));
+      for (int j = 0; j < d; ++j) {
+        // omega^{b j} = (Z[j][j])^b, taken from the reduced exponent b j mod d
+        const int e = (b * j) % d;
+        // Z[e][e] holds omega^e
+        at(b, j, j)[0] = w * Z[2 * (size_t(e) * d + e)];
+        at(b, j, j)[1] = w * Z[2 * (size_t(e) * d + e) + 1];
+      }
+    }
+    return QD_OK;
+  }
+  // depolarizing: K_ab = w_ab X^a Z^b, (X^a Z^b)[r][c] = omega^{b c} when r = c + a mod d
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      const double w = (a == 0 && b == 0) ? std::sqrt(1.0 - p + p / (double(d) * d)) : std::sqrt(p / (double(d) * d));
+      const int q = a * d + b;
+      for (int c = 0; c < d; ++c) {
+        const int r = (c + a) % d, e = (b * c) % d;
+        at(q, r, c)[0] = w * Z[2 * (size_t(e) * d + e)];
+        at(q, r, c)[1] = w * Z[2 * (size_t(e) * d + e) + 1];
+      }
+    }
+  return QD_OK;
+}
+
+int qd_density_trace(qd_state* rho, double* re, double* im) {
+  if (!rho || !re || !im) return fail(QD_EINVAL, "null argument");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  Register phys{};
+  int rc = make_register(rho->reg.dims, rho->dens_n, &phys);
+  if (rc) return rc;
+  const uint64_t Dp = uint64_t(phys.D);
+  const unsigned g = red_grid(Dp);
+  double* part = nullptr;
+  QD_HIP(hipMalloc((void**)&part, size_t(g) * 2 * sizeof(double)));
+  if (rho->prec == QD_C128)
+    hipLaunchKernelGGL(k_trace_part<double>, dim3(g), dim3(kBlock), 0, rho->stream, (const double*)rho->data, Dp, part);
+  else
+    hipLaunchKernelGGL(k_trace_part<float>, dim3(g), dim3(kBlock), 0, rho->stream, (const float*)rho->data, Dp, part);
+  double o[2];
+  rc = finish(rho, part, g, 2, o);
+  if (rc) return rc;
+  *re = o[0];
+  *im = o[1];
+  return QD_OK;
+}
+
+int qd_density_probabilities(qd_state* rho, double* out, int32_t out_is_device) {
+  if (!rho || !out) return fail(QD_EINVAL, "null argument");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  Register phys{};
+  int rc = make_register(rho->reg.dims, rho->dens_n, &phys);
+  if (rc) return rc;
+  const uint64_t D = uint64_t(phys.D);
+  double* dst = out;
+  if (!out_is_device) QD_HIP(hipMalloc((void**)&dst, D * sizeof(double)));
+  const dim3 grid(unsigned((D + kBlock - 1) / kBlock));
+  if (rho->prec == QD_C128)
+    hipLaunchKernelGGL(k_diag<double>, grid, dim3(kBlock), 0, rho->stream, (const double*)rho->data, D, dst);
+  else
+    hipLaunchKernelGGL(k_diag<float>, grid, dim3(kBlock), 0, rho->stream, (const float*)rho->data, D, dst);
+  hipError_t e = hipGetLastError();
+  if (!out_is_device) {
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dst, D * sizeof(double), hipMemcpyDeviceToHost, rho->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(rho->stream);
+    (void)hipFree(dst);
+  } else if (e == hipSuccess) {
+    e = hipStreamSynchronize(rho->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "qd_density_probabilities");
+  return QD_OK;
+}
+
+int qd_density_purity(qd_state* rho, double* out) {
+  if (!rho || !out) return fail(QD_EINVAL, "null argument");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  return reduce_norm2(rho, out);     // tr(rho^2) = sum |rho_xy|^2 for a Hermitian rho
+}
+
+int qd_density_fidelity(qd_state* rho, const qd_state* psi, double* out) {
+  if (!rho || !psi || !out) return fail(QD_EINVAL, "null argument");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  if (!same_register(rho, psi)) return fail(QD_EDIM, "the state's register differs from the density matrix's");
+  if (psi->prec != rho->prec) return fail(QD_EINVAL, "the state and the density matrix differ in precision");
+  QD_HIP(hipStreamSynchronize(psi->stream));
+  const uint64_t D = uint64_t(psi->reg.D);
+  const unsigned g = unsigned(std::max<uint64_t>(1, std::min<uint64_t>(kRedGrid, D)));
+  double* part = nullptr;
+  QD_HIP(hipMalloc((void**)&part, size_t(g) * 2 * sizeof(double)));
+  if (rho->prec == QD_C128)
+    hipLaunchKernelGGL(k_fidelity_part<double>, dim3(g), dim3(kBlock), 0, rho->stream, (const double*)rho->data,
+                       (const double*)psi->data, D, part);
+  else
+    hipLaunchKernelGGL(k_fidelity_part<float>, dim3(g), dim3(kBlock), 0, rho->stream, (const float*)rho->data,
+                       (const float*)psi->data, D, part);
+  double o[2];
+  int rc = finish(rho, part, g, 2, o);
+  if (rc) return rc;
+  *out = o[0];
+  return QD_OK;
+}
+
+int qd_density_size(const qd_state* rho, int32_t* n_qudits) {
+  if (!rho || !n_qudits) return fail(QD_EINVAL, "null argument");
+  *n_qudits = rho->dens_n;
+  return QD_OK;
+}
+
+}  // extern "C"

@@ -121,6 +121,7 @@ struct qd_state {
   size_t red_cap = 0;         // in doubles
   void* mws = nullptr;        // measurement workspace (sums of weights, marginal partials, staging)
   size_t mws_cap = 0;         // in bytes
+  int dens_n = 0;             // density matrix over dens_n qudits (register = dims ++ dims), else 0
 };
 
 namespace qd {

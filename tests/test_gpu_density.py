@@ -1,0 +1,197 @@
+"""GPU density matrices (qd_density_*) against the density oracle (full operators and matrix
+products), and at benchmark size against the GPU state-vector path and properties that hold at any
+size: trace, Hermiticity, purity and the fidelity of a noise-free evolution."""
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+from oracle import density as Dm
+import paper_2211_07918_amd as Q
+from gpu_util import torch_stream
+
+pytestmark = pytest.mark.gpu
+
+MAKERS = {Q.QD_CHANNEL_DEPOLARIZING: Dm.depolarizing, Q.QD_CHANNEL_DEPHASING: Dm.dephasing,
+          Q.QD_CHANNEL_AMPLITUDE_DAMPING: Dm.amplitude_damping}
+
+
+@pytest.fixture(scope="module")
+def stream():
+    return torch_stream()
+
+
+def download_rho(rho, dims):
+    D = int(np.prod(dims))
+    return Q.qd_state_download(rho).reshape(D, D)
+
+
+def noisy_program(dims, ngates, rng, p=0.08):
+    """Gates from the random-circuit sampler, each followed by a named channel on its first target;
+    every fifth step a joint two-qudit channel (products of one-qudit Kraus sets)."""
+    circ = C.random_circuit(dims, ngates, rng, max_targets=2, max_controls=2)
+    prog = []
+    kinds = list(MAKERS)
+    for i, g in enumerate(circ.gates):
+        prog.append(("gate", g))
+        q = g.targets[0]
+        kind = kinds[int(rng.integers(3))]
+        prog.append(("chan", (q,), kind, p))
+        if i % 5 == 4 and len(dims) > 1:
+            a, b = [int(x) for x in rng.choice(len(dims), 2, replace=False)]
+            if dims[a] * dims[b] <= 32:
+                prog.append(("joint", (a, b), p))
+    return prog
+
+
+def run_oracle(dims, prog, rho):
+    for op in prog:
+        if op[0] == "gate":
+            g = op[1]
+            rho = Dm.apply_unitary(rho, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+        elif op[0] == "chan":
+            _, t, kind, p = op
+            rho = Dm.apply_channel(rho, dims, t, MAKERS[kind](dims[t[0]], p))
+        else:
+            _, (a, b), p = op
+            ks = [np.kron(x, y) for x in Dm.dephasing(dims[a], p) for y in Dm.depolarizing(dims[b], p)]
+            rho = Dm.apply_channel(rho, dims, (a, b), ks)
+    return rho
+
+
+def run_gpu(dims, prog, rho_h):
+    for op in prog:
+        if op[0] == "gate":
+            Q.apply_circuit_gate_density(rho_h, op[1], dims)
+        elif op[0] == "chan":
+            _, t, kind, p = op
+            Q.qd_density_apply_channel(rho_h, t, Q.qd_channel_kraus(kind, dims[t[0]], p))
+        else:
+            _, (a, b), p = op
+            ka = Q.qd_channel_kraus(Q.QD_CHANNEL_DEPHASING, dims[a], p)
+            kb = Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, dims[b], p)
+            Q.qd_density_apply_channel(rho_h, (a, b), [np.kron(x, y) for x in ka for y in kb])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_noisy_circuits_match_the_oracle(stream, seed):
+    rng = np.random.default_rng(600 + seed)
+    dims = tuple(int(x) for x in rng.integers(2, 5, size=int(rng.integers(2, 5))))
+    prog = noisy_program(dims, 12, rng)
+    want = run_oracle(dims, prog, Dm.from_state(O.basis_state(dims)))
+    rho = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        run_gpu(dims, prog, rho)
+        got = download_rho(rho, dims)
+        assert np.max(np.abs(got - want)) <= 1e-12
+        assert abs(Q.qd_density_trace(rho) - Dm.trace(want)) <= 1e-13
+        assert np.max(np.abs(Q.qd_density_probabilities(rho) - Dm.probabilities(want))) <= 1e-13
+        assert abs(Q.qd_density_purity(rho) - Dm.purity(want)) <= 1e-12
+    finally:
+        Q.qd_state_free(rho)
+
+
+def test_from_state_and_fidelity(stream):
+    rng = np.random.default_rng(7)
+    dims = (3, 2, 4, 2)
+    D = int(np.prod(dims))
+    psi0 = C.random_basis_superposition(D, 20, rng)
+    circ = C.random_circuit(dims, 10, rng)
+    psi = O.run_circuit(circ, psi0)
+    s = Q.qd_state_init(dims, Q.QD_C128, stream)
+    rho = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        Q.qd_state_upload(s, psi0)
+        Q.qd_density_from_state(rho, s)
+        assert np.max(np.abs(download_rho(rho, dims) - Dm.from_state(psi0))) <= 1e-15
+        for g in circ.gates:
+            Q.apply_circuit_gate_density(rho, g, dims)
+        Q.qd_state_upload(s, psi)
+        assert abs(Q.qd_density_fidelity(rho, s) - 1.0) <= 1e-12
+        Q.qd_density_apply_channel(rho, (1,), Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, 2, 0.5))
+        want = Dm.apply_channel(Dm.from_state(psi), dims, (1,), Dm.depolarizing(2, 0.5))
+        assert abs(Q.qd_density_fidelity(rho, s) - Dm.fidelity(want, psi)) <= 1e-12
+    finally:
+        Q.qd_state_free(s)
+        Q.qd_state_free(rho)
+
+
+def test_complex64_density(stream):
+    rng = np.random.default_rng(8)
+    dims = (2, 3, 3)
+    prog = noisy_program(dims, 10, rng)
+    want = run_oracle(dims, prog, Dm.from_state(O.basis_state(dims)))
+    rho = Q.qd_density_init(dims, Q.QD_C64, stream)
+    try:
+        run_gpu(dims, prog, rho)
+        assert np.max(np.abs(download_rho(rho, dims) - want)) <= 1e-6
+    finally:
+        Q.qd_state_free(rho)
+
+
+def test_errors(stream):
+    dims = (2, 3)
+    rho = Q.qd_density_init(dims, Q.QD_C128, stream)
+    s = Q.qd_state_init((3, 2), Q.QD_C128, stream)
+    try:
+        bad = [0.5 * np.eye(2, dtype=np.complex128)]                 # not trace preserving
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_density_apply_channel(rho, (0,), bad)
+        assert e.value.code == Q.QD_ENOTUNITARY
+        Q.qd_density_apply_channel(rho, (0,), bad, Q.QD_FLAG_SKIP_UNITARY_CHECK)   # allowed when asked
+        assert abs(Q.qd_density_trace(rho) - 0.25) <= 1e-15
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_density_from_state(rho, s)                            # other register
+        assert e.value.code == Q.QD_EDIM
+        with pytest.raises(Q.QDError):
+            Q.qd_density_apply_channel(s, (0,), [np.eye(3)])           # not a density matrix
+        with pytest.raises(Q.QDError):
+            Q.qd_density_apply_gate(rho, (0,), (0,), (1,), O.x_gate(2))  # control repeats the target
+    finally:
+        Q.qd_state_free(rho)
+        Q.qd_state_free(s)
+
+
+def test_channel_dimension_limit(stream):
+    dims = (4, 3, 3)
+    rho = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        ks = [np.eye(36, dtype=np.complex128)]
+        with pytest.raises(Q.QDError) as e:             # d_T = 36 > 32
+            Q.qd_density_apply_channel(rho, (0, 1, 2), ks)
+        assert e.value.code == Q.QD_EDIM
+    finally:
+        Q.qd_state_free(rho)
+
+
+def test_benchmark_size_pure_and_noisy(stream):
+    """7 qubits + 4 qutrits (D = 10,368, 1.07e8 elements): a noise-free evolution of a random
+    superposition must stay pure and give fidelity 1 with the GPU state-vector result; with
+    depolarizing noise after every gate the trace stays 1 and the purity drops."""
+    rng = C.seeded_rng(1007)
+    dims = (2,) * 7 + (3,) * 4
+    D = int(np.prod(dims))
+    circ = C.random_circuit(dims, 30, rng, max_targets=1, max_controls=1)
+    psi0 = C.random_basis_superposition(D, 64, rng)
+    s = Q.qd_state_init(dims, Q.QD_C128, stream)
+    rho = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        Q.qd_state_upload(s, psi0)
+        Q.qd_density_from_state(rho, s)
+        for g in circ.gates:
+            Q.apply_circuit_gate(s, g, dims)
+            Q.apply_circuit_gate_density(rho, g, dims)
+        assert abs(Q.qd_density_fidelity(rho, s) - 1.0) <= 1e-10
+        assert abs(Q.qd_density_purity(rho) - 1.0) <= 1e-10
+        for g in circ.gates[:10]:
+            t = g.targets[0]
+            Q.qd_density_apply_channel(rho, (t,), Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, dims[t], 0.05))
+        tr = Q.qd_density_trace(rho)
+        assert abs(tr - 1.0) <= 1e-12
+        pur = Q.qd_density_purity(rho)
+        assert 1.0 / D <= pur < 1.0 - 1e-3
+        p = Q.qd_density_probabilities(rho)
+        assert np.min(p) >= -1e-15 and abs(np.sum(p) - 1.0) <= 1e-12
+    finally:
+        Q.qd_state_free(s)
+        Q.qd_state_free(rho)
