@@ -276,6 +276,15 @@ struct RunQudit {
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
 
 // Each thread carries E entries; entry i's digit of qudit q sits at dig[(q * E + i) * kBlock + lane].
+// Gate descriptors are read from device memory with scalar loads (uniform), one gate ahead; the
+// tables of table gates are staged in LDS and read per lane.
+template <int E>
+__device__ __forceinline__ void control_check(const uint8_t* my, uint32_t cq, uint32_t cv, bool (&ok)[E]) {
+  constexpr int QS = E * kBlock;
+#pragma unroll
+  for (int i = 0; i < E; ++i) ok[i] = ok[i] & (uint32_t(my[cq * QS + i * kBlock]) == cv);
+}
+
 template <bool UNIT, int kRunE>
 __global__ __launch_bounds__(kBlock) void k_mono_run(const int64_t* __restrict__ cnt, int64_t* __restrict__ idx,
                                                      double2* __restrict__ amp, const uint4* __restrict__ stage,
@@ -283,115 +292,104 @@ __global__ __launch_bounds__(kBlock) void k_mono_run(const int64_t* __restrict__
                                                      int32_t o_un, const RunQudit* __restrict__ rq, int32_t nq,
                                                      int64_t* __restrict__ upd) {
   extern __shared__ uint4 lds[];
-  for (int i = threadIdx.x; i < stage16; i += kBlock) lds[i] = stage[i];
+  // tables only (the descriptors are read from device memory below)
+  const int32_t t16 = (o_nd / 16);
+  for (int i = t16 + int(threadIdx.x); i < stage16; i += kBlock) lds[i] = stage[i];
   const uint8_t* stg = reinterpret_cast<const uint8_t*>(lds);
-  const uint4* gd = lds;                                               // two uint4 per gate
   const uint32_t* nd = reinterpret_cast<const uint32_t*>(stg + o_nd);
   const double2* ph = reinterpret_cast<const double2*>(stg + o_ph);
   const uint8_t* un = stg + o_un;
+  const uint4* gdesc = stage;                                          // two uint4 per gate
   uint8_t* my = reinterpret_cast<uint8_t*>(lds + stage16) + threadIdx.x;
   constexpr int QS = kRunE * kBlock;                                   // stride between qudits
   __syncthreads();
   const int64_t n = *cnt;
-  int hits = 0;
+  uint32_t hits = 0;                                                   // uniform: counted by ballots
   for (int64_t b0 = int64_t(blockIdx.x) * (kRunE * kBlock); b0 < n; b0 += int64_t(gridDim.x) * (kRunE * kBlock)) {
     int64_t e[kRunE];
     bool active[kRunE];
-    uint64_t t[kRunE];
+    uint64_t x0[kRunE];
 #pragma unroll
     for (int i = 0; i < kRunE; ++i) {
       e[i] = b0 + i * kBlock + threadIdx.x;
       active[i] = e[i] < n;
-      t[i] = active[i] ? uint64_t(__builtin_nontemporal_load(idx + e[i])) : 0;
+      x0[i] = active[i] ? uint64_t(__builtin_nontemporal_load(idx + e[i])) : 0;
     }
-    for (int q = nq - 1; q >= 0; --q) {
-      const RunQudit r = rq[q];
+    {
+      uint64_t t[kRunE];
 #pragma unroll
-      for (int i = 0; i < kRunE; ++i) {
-        const uint64_t qt = mdiv(t[i], r.md);
-        my[q * QS + i * kBlock] = uint8_t(t[i] - qt * r.d);
-        t[i] = qt;
+      for (int i = 0; i < kRunE; ++i) t[i] = x0[i];
+      for (int q = nq - 1; q >= 0; --q) {
+        const RunQudit r = rq[q];
+#pragma unroll
+        for (int i = 0; i < kRunE; ++i) {
+          const uint64_t qt = mdiv(t[i], r.md);
+          my[q * QS + i * kBlock] = uint8_t(t[i] - qt * r.d);
+          t[i] = qt;
+        }
       }
     }
     double2 a[kRunE];
     bool changed[kRunE];
-    int eh[kRunE];
 #pragma unroll
     for (int i = 0; i < kRunE; ++i) {
       a[i] = make_double2(0.0, 0.0);
       if (!UNIT && active[i]) a[i] = amp[e[i]];
       changed[i] = false;
-      eh[i] = 0;
     }
-    uint4 A = gd[0], B = gd[1];
     for (int gi = 0; gi < ngates; ++gi) {
-      const uint4 cA = A, cB = B;
-      if (gi + 1 < ngates) {                                           // next descriptor in flight
-        A = gd[2 * gi + 2];
-        B = gd[2 * gi + 3];
-      }
-      const uint32_t w0 = __builtin_amdgcn_readfirstlane(cA.x);
-      const uint32_t m = byte_of(w0, 2);
-      const uint32_t tqw = __builtin_amdgcn_readfirstlane(cA.y), tdw = __builtin_amdgcn_readfirstlane(cA.z);
+      const uint4 A = gdesc[2 * gi], B = gdesc[2 * gi + 1];           // scalar loads (uniform address)
+      const uint32_t w0 = A.x, m = byte_of(w0, 2), shift = byte_of(w0, 0);
       bool ok[kRunE];
 #pragma unroll
       for (int i = 0; i < kRunE; ++i) ok[i] = active[i];
-      if (m) {
-        const uint32_t c0 = __builtin_amdgcn_readfirstlane(cA.w), c1 = __builtin_amdgcn_readfirstlane(cB.x);
-        const uint32_t v0 = __builtin_amdgcn_readfirstlane(cB.y), v1 = __builtin_amdgcn_readfirstlane(cB.z);
-        for (uint32_t j = 0; j < m; ++j) {
-          const uint32_t cq = byte_of(j < 4 ? c0 : c1, int(j & 3));
-          const uint32_t cv = byte_of(j < 4 ? v0 : v1, int(j & 3));
+      if (m >= 1) control_check<kRunE>(my, byte_of(A.w, 0), byte_of(B.y, 0), ok);
+      if (m >= 2) control_check<kRunE>(my, byte_of(A.w, 1), byte_of(B.y, 1), ok);
+      for (uint32_t j = 2; j < m; ++j)
+        control_check<kRunE>(my, byte_of(j < 4 ? A.w : B.x, int(j & 3)), byte_of(j < 4 ? B.y : B.z, int(j & 3)), ok);
 #pragma unroll
-          for (int i = 0; i < kRunE; ++i) ok[i] = ok[i] & (uint32_t(my[cq * QS + i * kBlock]) == cv);
-        }
-      }
-      const uint32_t shift = byte_of(w0, 0);
+      for (int i = 0; i < kRunE; ++i) hits += uint32_t(__popcll(__ballot(ok[i])));
       if (shift) {
-        const uint32_t q = byte_of(tqw, 0), d = byte_of(tdw, 0) + 1;
+        const uint32_t q = byte_of(A.y, 0), d = byte_of(A.z, 0) + 1;
 #pragma unroll
         for (int i = 0; i < kRunE; ++i) {
           if (ok[i]) {
             uint8_t* dq = my + q * QS + i * kBlock;
-            uint32_t v = uint32_t(*dq) + shift;
-            if (v >= d) v -= d;
-            *dq = uint8_t(v);
-            ++eh[i];
+            const uint32_t v = uint32_t(*dq) + shift;
+            *dq = uint8_t(v >= d ? v - d : v);
           }
         }
       } else {
         const uint32_t k = byte_of(w0, 1);
-        const int32_t tab = int32_t(__builtin_amdgcn_readfirstlane(cB.w));
+        const int32_t tab = int32_t(B.w);
 #pragma unroll
         for (int i = 0; i < kRunE; ++i) {
           if (ok[i]) {
             uint32_t loc = 0;
             for (uint32_t j = 0; j < k; ++j)
-              loc = loc * (byte_of(tdw, int(j)) + 1) + my[byte_of(tqw, int(j)) * QS + i * kBlock];
+              loc = loc * (byte_of(A.z, int(j)) + 1) + my[byte_of(A.y, int(j)) * QS + i * kBlock];
             const int32_t ti = tab + int32_t(loc);
             const uint32_t nw = nd[ti];
-            for (uint32_t j = 0; j < k; ++j) my[byte_of(tqw, int(j)) * QS + i * kBlock] = uint8_t(nw >> (8 * j));
+            for (uint32_t j = 0; j < k; ++j) my[byte_of(A.y, int(j)) * QS + i * kBlock] = uint8_t(nw >> (8 * j));
             if (!UNIT && !un[ti]) {
               a[i] = cmul(ph[ti], a[i]);
               changed[i] = true;
             }
-            ++eh[i];
           }
         }
       }
     }
 #pragma unroll
     for (int i = 0; i < kRunE; ++i) {
-      if (eh[i]) {
-        uint64_t x = 0;
-        for (int q = 0; q < nq; ++q) x += uint64_t(my[q * QS + i * kBlock]) * uint64_t(rq[q].stride);
-        __builtin_nontemporal_store(int64_t(x), idx + e[i]);
-        if (!UNIT && changed[i]) amp[e[i]] = a[i];
-      }
-      hits += eh[i];
+      if (!active[i]) continue;
+      uint64_t x = 0;
+      for (int q = 0; q < nq; ++q) x += uint64_t(my[q * QS + i * kBlock]) * uint64_t(rq[q].stride);
+      if (x != x0[i]) __builtin_nontemporal_store(int64_t(x), idx + e[i]);
+      if (!UNIT && changed[i]) amp[e[i]] = a[i];
     }
   }
-  wave_count(hits, upd);
+  if ((threadIdx.x & 63) == 0 && hits)
+    atomicAdd(reinterpret_cast<unsigned long long*>(upd + (blockIdx.x & (kUpdSlots - 1))), (unsigned long long)hits);
 }
 
 // ------------------------------------------------------------------------------------------ dense gates
