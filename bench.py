@@ -482,31 +482,29 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
     D = int(np.prod(dims))
     circ, ops = _noisy_ops(C, dims, 60, 1008)
     kraus = {d: Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, d, 1e-3) for d in set(dims)}
-    unit = {id(g): Q.gate_unitary(g, dims) for g in circ.gates}
-    # passes, as the library forms them: one for a channel and for a gate whose embedding on its
-    # targets and controls has d_G <= 3 (dense U) or <= 4 (monomial or diagonal U); two otherwise,
-    # each touching the D^2 / d_c elements whose (row or column) control digits match
+    lib_ops = [o if o[0] == "gate" else ("chan", (o[1],), kraus[dims[o[1]]]) for o in ops]
+    # passes, as qd_density_apply_ops forms them: an uncontrolled gate on a qubit or qutrit and the
+    # channel after it are one composed pass; otherwise a channel is one pass and a gate one pass
+    # when its embedding on targets and controls has d_G <= 3 (dense U) or <= 4 (monomial or
+    # diagonal U), else two, each touching the D^2 / d_c elements whose control digits match
     passes, active = 0, 0
-    for o in ops:
-        if o[0] == "chan":
+    for g in circ.gates:
+        t = g.targets[0]
+        if not g.controls and dims[t] <= 3:
             passes += 1
             active += D * D
             continue
-        g = o[1]
+        passes += 1
+        active += D * D                                # the channel
         dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
-        dG = dims[g.targets[0]] * dc
-        fused = dG <= (4 if Q.qd_gate_class(unit[id(g)]) != Q.QD_CLASS_DENSE else 3)
+        dG = dims[t] * dc
+        fused = dG <= (4 if Q.qd_gate_class(Q.gate_unitary(g, dims)) != Q.QD_CLASS_DENSE else 3)
         passes += 1 if fused else 2
         active += D * D if fused else 2 * (D * D // dc)
     rho = Q.qd_density_init(dims, Q.QD_C128, st)
 
     def run():
-        for o in ops:
-            if o[0] == "gate":
-                g = o[1]
-                Q.qd_density_apply_gate(rho, g.targets, g.controls, g.cvals, unit[id(g)])
-            else:
-                Q.qd_density_apply_channel(rho, (o[1],), kraus[dims[o[1]]])
+        Q.qd_density_apply_ops(rho, lib_ops)
 
     run()                                              # warm-up
     e0, e1 = _ev(torch)
@@ -522,8 +520,10 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
     Q.qd_state_free(rho)
     alg = 2.0 * 16.0 * active
     out = {"workload": "density matrix, 7 qubits + 4 qutrits (D = 10,368), 60 gates + 60 depolarizing channels",
-           "elements": D * D, "passes": passes, "circuit_ms": ms, "ms_per_pass": ms / passes,
-           "element_updates_per_s": active / (ms * 1e-3), "trace_re": tr.real, "purity": pur,
+           "elements": D * D, "operations": len(ops), "passes": passes, "circuit_ms": ms, "ms_per_pass": ms / passes,
+           "element_updates_per_s": len(ops) * D * D / (ms * 1e-3),
+           "element_updates_unit": "one operation over all D^2 elements",
+           "trace_re": tr.real, "purity": pur,
            "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                         "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}}
     if cpu:
@@ -718,9 +718,10 @@ def main():
     if "density" in which:
         dn = bench_density(Q, torch, cpu=not args.no_cpu, cpu_seconds=min(args.cpu_seconds, 10.0))
         extras["density_noisy_circuit"] = dn
-        log(f"density: {dn['passes']} passes over {dn['elements']} elements in {dn['circuit_ms']:.1f} ms "
-            f"({dn['ms_per_pass']:.3f} ms/pass, {dn['roofline']['achieved']:.0f} GB/s = "
-            f"{100 * dn['roofline']['frac']:.0f}% of HBM peak), trace {dn['trace_re']:.12f}")
+        log(f"density: {dn['operations']} operations as {dn['passes']} passes over {dn['elements']} elements in "
+            f"{dn['circuit_ms']:.1f} ms ({dn['ms_per_pass']:.3f} ms/pass, {dn['roofline']['achieved']:.0f} GB/s = "
+            f"{100 * dn['roofline']['frac']:.0f}% of HBM peak, {dn['element_updates_per_s']:.3e} element updates/s), "
+            f"trace {dn['trace_re']:.12f}")
     if tuning:
         extras["tuning"] = tuning
     if args.extras_only:

@@ -473,6 +473,26 @@ int qd_density_apply_channel(qd_state* rho, const int32_t* targets, int32_t k, c
 enum { QD_CHANNEL_DEPOLARIZING = 0, QD_CHANNEL_DEPHASING = 1, QD_CHANNEL_AMPLITUDE_DAMPING = 2 };
 int qd_channel_kraus(int32_t kind, int32_t d, double p, double* out, int32_t cap, int32_t* nk);
 
+/* A sequence of density operations: QD_OP_GATE (targets, controls, control values and one d_T x d_T
+ * matrix U in mats, nk = 1) or QD_OP_CHANNEL (targets, no controls, nk Kraus operators in mats). */
+enum { QD_OP_GATE = 0, QD_OP_CHANNEL = 1 };
+typedef struct {
+  int32_t kind;
+  int32_t k;
+  const int32_t* targets;
+  int32_t m;
+  const int32_t* controls;
+  const int32_t* control_values;
+  int32_t nk;
+  const double* mats;
+} qd_density_op;
+
+/* Apply count operations in order, as qd_density_apply_gate / qd_density_apply_channel would, with
+ * every operation validated first. Consecutive operations on the same target list without controls
+ * and with d_T <= 3 (a gate and the channels that follow it, say) are composed on the host in FP64
+ * into one superoperator and applied in one pass. Asynchronous. */
+int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count, uint32_t flags);
+
 /* tr(rho) (both parts), fixed reduction order. Synchronises. */
 int qd_density_trace(qd_state* rho, double* re, double* im);
 

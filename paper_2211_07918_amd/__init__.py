@@ -26,6 +26,7 @@ __all__ = [
     "qd_density_init", "qd_density_from_state", "qd_density_apply_gate", "qd_density_apply_channel",
     "qd_channel_kraus", "qd_density_trace", "qd_density_probabilities", "qd_density_purity",
     "qd_density_fidelity", "qd_density_size", "qd_density_dims", "apply_circuit_gate_density",
+    "qd_density_apply_ops", "QD_OP_GATE", "QD_OP_CHANNEL",
     "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
     "QD_TUNE_BATCH_GRID",
@@ -58,6 +59,7 @@ QD_FLAG_SKIP_UNITARY_CHECK = 1
 QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
 QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2
 QD_CHANNEL_DEPOLARIZING, QD_CHANNEL_DEPHASING, QD_CHANNEL_AMPLITUDE_DAMPING = 0, 1, 2
+QD_OP_GATE, QD_OP_CHANNEL = 0, 1
 QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
  QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID) = range(10)
@@ -74,6 +76,12 @@ class QDError(RuntimeError):
 
 def lib_path() -> str:
     return os.path.join(_HERE, "libqd.so")
+
+
+class _DensityOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("targets", C.POINTER(C.c_int32)), ("m", C.c_int32),
+                ("controls", C.POINTER(C.c_int32)), ("control_values", C.POINTER(C.c_int32)),
+                ("nk", C.c_int32), ("mats", C.POINTER(C.c_double))]
 
 
 class _Gate(C.Structure):
@@ -160,6 +168,7 @@ _SIGS = {
     "qd_density_purity": (C.c_int, [_P, _DP]),
     "qd_density_fidelity": (C.c_int, [_P, _P, _DP]),
     "qd_density_size": (C.c_int, [_P, _I32P]),
+    "qd_density_apply_ops": (C.c_int, [_P, C.POINTER(_DensityOp), C.c_int32, C.c_uint32]),
     "qd_sparse_free": (None, [_P]),
     "qd_batch_create": (C.c_int, [C.c_int32, _I32P, _I32P, C.c_int32, _P, C.POINTER(_P)]),
     "qd_batch_size": (C.c_int, [_P, _I64P]),
@@ -653,6 +662,34 @@ def qd_density_apply_channel(rho: int, targets, kraus, flags: int = 0) -> None:
         _check_shape(qd_density_dims(rho), targets, K)
     flat = np.ascontiguousarray(np.concatenate([K.reshape(-1) for K in ks])) if ks else np.zeros(1, np.complex128)
     _check(load().qd_density_apply_channel(_P(rho), _i32(targets), len(targets), _dptr(flat), len(ks), int(flags)))
+
+
+def qd_density_apply_ops(rho: int, ops, flags: int = 0) -> None:
+    """Operations in order: ("gate", gate record) or ("chan", targets, [Kraus matrices])."""
+    dims = qd_density_dims(rho)
+    arr = (_DensityOp * max(1, len(ops)))()
+    keep = []
+    for i, o in enumerate(ops):
+        if o[0] == "gate":
+            g = o[1]
+            U = gate_unitary(g, dims)
+            _check_shape(dims, g.targets, U)
+            t, c, v = _i32(g.targets), _i32(g.controls), _i32(g.cvals)
+            keep += [U, t, c, v]
+            arr[i].kind, arr[i].k, arr[i].m, arr[i].nk = QD_OP_GATE, len(g.targets), len(g.controls), 1
+            arr[i].targets, arr[i].controls, arr[i].control_values = C.cast(t, _I32P), C.cast(c, _I32P), C.cast(v, _I32P)
+            arr[i].mats = _dptr(U)
+        else:
+            _, targets, kraus = o
+            ks = [_cplx(K) for K in kraus]
+            for K in ks:
+                _check_shape(dims, targets, K)
+            flat = np.ascontiguousarray(np.concatenate([K.reshape(-1) for K in ks]))
+            t = _i32(targets)
+            keep += [flat, t]
+            arr[i].kind, arr[i].k, arr[i].m, arr[i].nk = QD_OP_CHANNEL, len(targets), 0, len(ks)
+            arr[i].targets, arr[i].mats = C.cast(t, _I32P), _dptr(flat)
+    _check(load().qd_density_apply_ops(_P(rho), arr, len(ops), int(flags)))
 
 
 def qd_channel_kraus(kind: int, d: int, p: float) -> list:

@@ -34,6 +34,7 @@ constexpr int kBlock = 256;
 constexpr int kFuseGate = 3;          // dense U
 constexpr int kFuseMono = 4;          // monomial or diagonal U
 constexpr int kMaxChannelDim = 32;    // d_T of a channel (its superoperator is d_T^2 x d_T^2 <= 1024)
+constexpr int kFuseGroup = 3;         // d_T up to which a run of operations on the same targets is one pass
 constexpr int kRedGrid = 1024;
 
 template <typename R> struct Cx;
@@ -369,6 +370,118 @@ int qd_channel_kraus(int32_t kind, int32_t d, double p, double* out, int32_t cap
         at(q, r, c)[1] = w * Z[2 * (size_t(e) * d + e) + 1];
       }
     }
+  return QD_OK;
+}
+
+int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count, uint32_t flags) {
+  if (!rho) return fail(QD_EINVAL, "null state");
+  if (!rho->dens_n) return fail(QD_EINVAL, "not a density matrix");
+  if (count < 0 || (count > 0 && !ops)) return fail(QD_EINVAL, "null operations or negative count");
+  const int n = rho->dens_n;
+  Register phys{};
+  int rc = make_register(rho->reg.dims, n, &phys);
+  if (rc) return rc;
+  // validate everything before any device work
+  for (int32_t i = 0; i < count; ++i) {
+    const qd_density_op& o = ops[i];
+    if (o.kind == QD_OP_GATE) {
+      if (o.nk != 1 || !o.mats) return fail(QD_EINVAL, "a gate operation carries one matrix");
+      rc = validate_gate(phys, o.targets, o.k, o.controls, o.control_values, o.m, o.mats, flags);
+    } else if (o.kind == QD_OP_CHANNEL) {
+      if (o.m != 0) return fail(QD_EINVAL, "a channel operation has no controls");
+      if (!o.mats || o.nk < 1) return fail(QD_EINVAL, "a channel needs at least one Kraus operator");
+      // reuse the channel's own checks on a scratch-free path: targets, d_T and completeness
+      if (!o.targets || o.k < 1 || o.k > n) return fail(QD_EINVAL, "bad target list");
+      bool used[QD_MAX_QUDITS] = {};
+      int dT = 1;
+      for (int j = 0; j < o.k; ++j) {
+        if (o.targets[j] < 0 || o.targets[j] >= n || used[o.targets[j]]) return fail(QD_EINVAL, "bad target list");
+        used[o.targets[j]] = true;
+        dT *= phys.dims[o.targets[j]];
+        if (dT > kMaxChannelDim) return fail(QD_EDIM, "channel dimension d_T exceeds 32");
+      }
+      const size_t kk = size_t(dT) * dT;
+      for (size_t q = 0; q < 2 * kk * size_t(o.nk); ++q)
+        if (!std::isfinite(o.mats[q])) return fail(QD_ENOTUNITARY, "a Kraus operator has a NaN or Inf entry");
+      if (!(flags & QD_FLAG_SKIP_UNITARY_CHECK)) {
+        for (int a = 0; a < dT; ++a)
+          for (int b = 0; b < dT; ++b) {
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < o.nk; ++q) {
+              const double* K = o.mats + 2 * kk * size_t(q);
+              for (int l = 0; l < dT; ++l) {
+                const double ar = K[2 * (l * dT + a)], ai = -K[2 * (l * dT + a) + 1];
+                const double br = K[2 * (l * dT + b)], bi = K[2 * (l * dT + b) + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+              }
+            }
+            if (a == b) re -= 1.0;
+            if (std::sqrt(re * re + im * im) > 1e-10) return fail(QD_ENOTUNITARY, "Kraus operators do not sum to the identity");
+          }
+      }
+      rc = QD_OK;
+    } else {
+      return fail(QD_EINVAL, "unknown operation kind");
+    }
+    if (rc) return rc;
+  }
+  const uint32_t skip = flags | QD_FLAG_SKIP_UNITARY_CHECK;
+  auto dim_of = [&](const qd_density_op& o) {
+    int d = 1;
+    for (int j = 0; j < o.k; ++j) d *= phys.dims[o.targets[j]];
+    return d;
+  };
+  auto fusable = [&](const qd_density_op& o) { return o.m == 0 && dim_of(o) <= kFuseGroup; };
+  auto same_targets = [&](const qd_density_op& a, const qd_density_op& b) {
+    if (a.k != b.k) return false;
+    for (int j = 0; j < a.k; ++j)
+      if (a.targets[j] != b.targets[j]) return false;
+    return true;
+  };
+  int32_t i = 0;
+  while (i < count) {
+    const qd_density_op& o = ops[i];
+    int32_t e = i + 1;
+    if (fusable(o))
+      while (e < count && fusable(ops[e]) && same_targets(ops[e], o)) ++e;
+    if (e - i == 1) {
+      rc = o.kind == QD_OP_GATE
+               ? qd_density_apply_gate(rho, o.targets, o.k, o.controls, o.control_values, o.m, o.mats, skip)
+               : qd_density_apply_channel(rho, o.targets, o.k, o.mats, o.nk, skip);
+      if (rc) return rc;
+      i = e;
+      continue;
+    }
+    // compose S = S_{e-1} ... S_i in FP64: a gate contributes U (x) conj(U), a channel
+    // sum_k K_k (x) conj(K_k)
+    const int dT = dim_of(o), N = dT * dT;
+    std::vector<double> S(2 * size_t(N) * N, 0.0), T, P(2 * size_t(N) * N);
+    for (int r = 0; r < N; ++r) S[2 * (size_t(r) * N + r)] = 1.0;
+    for (int32_t q = i; q < e; ++q) {
+      const qd_density_op& g = ops[q];
+      T = superoperator(g.mats, g.kind == QD_OP_GATE ? 1 : g.nk, dT);
+      // P = T * S
+      for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) {
+          double re = 0.0, im = 0.0;
+          for (int l = 0; l < N; ++l) {
+            const double ar = T[2 * (size_t(r) * N + l)], ai = T[2 * (size_t(r) * N + l) + 1];
+            const double br = S[2 * (size_t(l) * N + c)], bi = S[2 * (size_t(l) * N + c) + 1];
+            re += ar * br - ai * bi;
+            im += ar * bi + ai * br;
+          }
+          P[2 * (size_t(r) * N + c)] = re;
+          P[2 * (size_t(r) * N + c) + 1] = im;
+        }
+      S.swap(P);
+    }
+    std::vector<int32_t> t2(o.targets, o.targets + o.k);
+    for (int j = 0; j < o.k; ++j) t2.push_back(o.targets[j] + n);
+    rc = qd_apply_gate_ex(rho, t2.data(), 2 * o.k, nullptr, nullptr, 0, S.data(), QD_FLAG_SKIP_UNITARY_CHECK);
+    if (rc) return rc;
+    i = e;
+  }
   return QD_OK;
 }
 

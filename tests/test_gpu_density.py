@@ -195,3 +195,43 @@ def test_benchmark_size_pure_and_noisy(stream):
     finally:
         Q.qd_state_free(s)
         Q.qd_state_free(rho)
+
+
+def test_operation_sequences_fuse_and_match(stream):
+    """qd_density_apply_ops composes runs of uncontrolled operations on the same targets into one
+    superoperator; the result matches the oracle and the one-by-one calls."""
+    rng = np.random.default_rng(31)
+    dims = (3, 2, 3, 2)
+    circ = C.random_circuit(dims, 16, rng, max_targets=1, max_controls=1)
+    ops = []
+    for g in circ.gates:
+        ops.append(("gate", g))
+        t = g.targets[0]
+        ops.append(("chan", (t,), Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, dims[t], 0.1)))
+        ops.append(("chan", (t,), Q.qd_channel_kraus(Q.QD_CHANNEL_AMPLITUDE_DAMPING, dims[t], 0.05)))
+    want = Dm.from_state(O.basis_state(dims))
+    for o in ops:
+        if o[0] == "gate":
+            g = o[1]
+            want = Dm.apply_unitary(want, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+        else:
+            want = Dm.apply_channel(want, dims, o[1], o[2])
+    a = Q.qd_density_init(dims, Q.QD_C128, stream)
+    b = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        Q.qd_density_apply_ops(a, ops)
+        for o in ops:
+            if o[0] == "gate":
+                Q.apply_circuit_gate_density(b, o[1], dims)
+            else:
+                Q.qd_density_apply_channel(b, o[1], o[2])
+        ga, gb = download_rho(a, dims), download_rho(b, dims)
+        assert np.max(np.abs(ga - want)) <= 1e-12 and np.max(np.abs(gb - want)) <= 1e-12
+        bad = ops[:3] + [("chan", (0,), [0.5 * np.eye(3)])]              # rejected before any work
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_density_apply_ops(a, bad)
+        assert e.value.code == Q.QD_ENOTUNITARY
+        assert np.array_equal(download_rho(a, dims), ga)
+    finally:
+        Q.qd_state_free(a)
+        Q.qd_state_free(b)
