@@ -150,6 +150,10 @@ int validate_gate(const Register& r, const int32_t* targets, int32_t k, const in
 int classify(const double* U, int dT);
 void make_plan(const Register& r, const int32_t* targets, int32_t k, const int32_t* controls,
                const int32_t* cvals, int32_t m, const double* U, GatePlan* p);
+// make_plan, with controls of stride below one 128-byte line folded into the targets when the
+// folded gate keeps a fast kernel (what qd_apply_gate launches)
+void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, const int32_t* controls,
+               const int32_t* cvals, int32_t m, const double* U, GatePlan* p);
 
 struct TileGeom {
   int pq = 0;          // first qudit of the low suffix staged in LDS

@@ -227,6 +227,47 @@ void make_plan(const Register& r, const int32_t* targets, int32_t k, const int32
   }
 }
 
+// A control whose stride is below one 128-byte line of amplitudes leaves every line partly
+// active: a pass over the matching slices still moves whole lines, and with its partial writes
+// such gates measured slower than a full pass (about 1 ms against 0.57 ms on a 1.7 GB state).
+// Those controls become targets of an embedded gate (U where they hold their values, the identity
+// elsewhere, exactly), which one coalesced pass applies, provided it keeps a fast kernel.
+void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, const int32_t* controls,
+               const int32_t* cvals, int32_t m, const double* U, GatePlan* p) {
+  make_plan(r, targets, k, controls, cvals, m, U, p);
+  const int64_t line = prec == QD_C128 ? 8 : 16;
+  std::vector<int> low, keep;
+  for (int j = 0; j < m; ++j) (r.strides[controls[j]] < line ? low : keep).push_back(j);
+  if (low.empty()) return;
+  int dC = 1;
+  for (int j : low) dC *= r.dims[controls[j]];
+  const int dT = p->dT, dG = dT * dC;
+  if (dG > QD_MAX_GATE_DIM) return;
+  int vidx = 0;                         // local index of the absorbed controls' values
+  for (int j : low) vidx = vidx * r.dims[controls[j]] + cvals[j];
+  std::vector<double> G(2 * size_t(dG) * dG, 0.0);
+  for (int c = 0; c < dC; ++c)
+    for (int t = 0; t < dT; ++t)
+      for (int t1 = 0; t1 < dT; ++t1) {
+        const size_t o = 2 * (size_t(t * dC + c) * dG + size_t(t1 * dC + c));
+        if (c == vidx) {
+          G[o] = U[2 * (size_t(t) * dT + t1)];
+          G[o + 1] = U[2 * (size_t(t) * dT + t1) + 1];
+        } else if (t == t1) {
+          G[o] = 1.0;
+        }
+      }
+  std::vector<int32_t> t2(targets, targets + k), c2, v2;
+  for (int j : low) t2.push_back(controls[j]);
+  for (int j : keep) {
+    c2.push_back(controls[j]);
+    v2.push_back(cvals[j]);
+  }
+  GatePlan q;
+  make_plan(r, t2.data(), int32_t(t2.size()), c2.data(), v2.data(), int32_t(c2.size()), G.data(), &q);
+  if (route_gate(r, prec, q) != QD_ROUTE_GENERIC) *p = std::move(q);
+}
+
 // ------------------------------------------------------------------------------------------ groups
 std::vector<Group> make_groups(const Register& r, const int* role, const uint32_t* lmul, int lo, int hi) {
   std::vector<Group> g;
@@ -346,7 +387,7 @@ int qd_gate_route(const int32_t* dims, int32_t n, int32_t prec, const int32_t* t
   rc = validate_gate(r, targets, k, controls, control_values, m, U, QD_FLAG_SKIP_UNITARY_CHECK);
   if (rc) return rc;
   GatePlan p;
-  make_plan(r, targets, k, controls, control_values, m, U, &p);
+  plan_gate(r, prec, targets, k, controls, control_values, m, U, &p);
   *route_out = route_gate(r, prec, p);
   return QD_OK;
 }
@@ -487,7 +528,7 @@ int qd_apply_gate_ex(qd_state* s, const int32_t* targets, int32_t k, const int32
   int rc = validate_gate(s->reg, targets, k, controls, control_values, m, U, flags);
   if (rc) return rc;
   GatePlan p;
-  make_plan(s->reg, targets, k, controls, control_values, m, U, &p);
+  plan_gate(s->reg, s->prec, targets, k, controls, control_values, m, U, &p);
   return launch_gate(s, p);
 }
 
