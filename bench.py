@@ -572,14 +572,17 @@ def bench_density_cpu(C, seconds):
 
 
 def bench_batch(Q, torch, ncirc=4096):
-    """4096 seeded circuits over uneven registers, 100 layers, complex64: one persistent launch per
-    layer recorded into a hipGraph, against the same gates applied one by one (plain path)."""
+    """4096 seeded circuits over uneven registers, 100 layers, complex64, recorded into a hipGraph:
+    one persistent launch per layer (fusion width 1) and each circuit's gates composed into
+    blocks of up to the autotuned fusion width, against the same gates applied one by one
+    (plain path)."""
     import numpy as np
     import circuits as C
     stream = torch.cuda.current_stream().cuda_stream
     circs = C.config4(ncirc)
     L = len(circs[0].gates)
     gas = [Q.GateArray([c.gates[l] for c in circs], lambda i: circs[i].dims) for l in range(L)]
+    flat = Q.GateArray([c.gates[l] for l in range(L) for c in circs], lambda j: circs[j % ncirc].dims)
     upd = 0
     for c in circs:
         for g in c.gates:
@@ -588,20 +591,26 @@ def bench_batch(Q, torch, ncirc=4096):
     Q.qd_batch_autotune(b, gas[0])
     block, spt = Q.qd_tune_get(Q.QD_TUNE_BATCH_BLOCK), Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT)
     grid = Q.qd_tune_get(Q.QD_TUNE_BATCH_GRID)
-    Q.qd_batch_capture(b, True)
-    for ga in gas:
-        Q.qd_batch_apply_layer(b, ga)
-    Q.qd_batch_capture(b, False)
-    Q.qd_batch_replay(b)
+    Q.qd_batch_autotune_layers(b, flat, L)
+    width = Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE)
     e0, e1 = _ev(torch)
     reps = 3
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
+
+    def graph_ms(w):
+        Q.qd_batch_capture(b, True)
+        Q.qd_batch_apply_layers(b, flat, L, w)
+        Q.qd_batch_capture(b, False)
         Q.qd_batch_replay(b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            Q.qd_batch_replay(b)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms1 = graph_ms(1)
+    ms = graph_ms(width) if width != 1 else ms1
     Q.qd_batch_free(b)
     # one by one: every gate of every circuit through qd_apply_gate on its own state
     states = [Q.qd_state_init(c.dims, Q.QD_C64, stream) for c in circs]
@@ -616,8 +625,9 @@ def bench_batch(Q, torch, ncirc=4096):
     for s in states:
         Q.qd_state_free(s)
     return {"circuits": ncirc, "layers": L, "sum_D": int(sum(c.D for c in circs)), "graph_ms": ms,
+            "fusion_width": width, "graph_ms_width1": ms1,
             "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
-            "hbm_GBps": 16.0 * upd / (ms * 1e-3) / 1e9, "one_by_one_s": one_s,
+            "hbm_GBps_width1": 16.0 * upd / (ms1 * 1e-3) / 1e9, "one_by_one_s": one_s,
             "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt,
             "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU"}
 
@@ -706,7 +716,8 @@ def main():
     if "batch" in which:
         extras["batched_4096_circuits"] = bench_batch(Q, torch)
         bb = extras["batched_4096_circuits"]
-        log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers, {bb['amp_upd_per_s']:.3e} amp-upd/s, "
+        log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers at fusion width {bb['fusion_width']} "
+            f"({bb['graph_ms_width1']:.1f} ms at width 1), {bb['amp_upd_per_s']:.3e} amp-upd/s, "
             f"x{bb['speedup_vs_one_by_one']:.1f} vs one by one")
     if "frontend" in which:
         fe = bench_frontend(Q)

@@ -530,6 +530,23 @@ int qd_batch_reset(qd_batch* b);
  * into the batch's graph instead of being run. */
 int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
 
+/* nlayers layers (gates[l * nc + c] acts on circuit c in layer l; k == 0 = no gate) with the
+ * gates of each circuit fused into blocks: a block takes the circuit's next gates in order while
+ * it has at most `width` of them (1..8; 0 = the tuned QD_TUNE_BATCH_FUSE) and the union of their
+ * qudits (targets and controls) has at most 4 qudits of total dimension in {2..9, 12, 16}. A
+ * block of several gates is composed on the host in FP64 into one operation on that union (each
+ * U embedded, the identity where its control misses) and applied in one pass over the state.
+ * Launch i applies every circuit's i-th block, so the launch count is the most blocks of any
+ * circuit. Gates are validated as in qd_batch_apply_layer before any device work. Recorded into
+ * the graph while capture is on. */
+int qd_batch_apply_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, int32_t width);
+
+/* Fusion-width autotuner: records qd_batch_apply_layers over the given layers into a graph for
+ * widths 1, 2, 3, 4, 6 and 8, times replays of each (host composition excluded) and keeps the
+ * fastest as QD_TUNE_BATCH_FUSE (saved by qd_tune_save). The arena is saved and restored and a
+ * graph the caller recorded is kept. Not allowed while recording. Synchronises. */
+int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers);
+
 /* on = 1 starts recording layers into a new graph (dropping any previous one); on = 0 ends the
  * recording and instantiates the graph. */
 int qd_batch_capture(qd_batch* b, int32_t on);
@@ -555,12 +572,13 @@ void qd_batch_free(qd_batch* b);
  * slice columns per fused tile (32, 64, 128), the target stride below which a gate is staged
  * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes) and the workgroups per compute unit of the batched
  * layer kernel (QD_TUNE_BATCH_GRID: 1..63 persistent workgroups walk the tile list; 64 launches one
- * workgroup per tile). 0 restores the default. Process-wide,
+ * workgroup per tile) and the most gates qd_batch_apply_layers composes into one operation
+ * (QD_TUNE_BATCH_FUSE, 1..8). 0 restores the default. Process-wide,
  * host only; QD_EINVAL for an unknown parameter or a value outside its range. */
 enum { QD_TUNE_DIRECT_BLOCK = 0, QD_TUNE_DIRECT_SPT = 1, QD_TUNE_TILE_BLOCK = 2,
        QD_TUNE_TILE_ELEMS = 3, QD_TUNE_DIAG_BLOCK = 4, QD_TUNE_BATCH_BLOCK = 5,
        QD_TUNE_BATCH_SPT = 6, QD_TUNE_FUSED_COLS = 7, QD_TUNE_RUN_MIN = 8, QD_TUNE_BATCH_GRID = 9,
-       QD_TUNE_COUNT = 10 };
+       QD_TUNE_BATCH_FUSE = 10, QD_TUNE_COUNT = 11 };
 int qd_tune_set(int32_t param, int32_t value);
 int qd_tune_get(int32_t param, int32_t* value);
 

@@ -29,7 +29,7 @@ __all__ = [
     "qd_density_apply_ops", "QD_OP_GATE", "QD_OP_CHANNEL",
     "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
-    "QD_TUNE_BATCH_GRID",
+    "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "qd_batch_apply_layers", "qd_batch_autotune_layers",
     "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "qd_gate_route",
     "qd_version", "qd_last_error", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
@@ -62,7 +62,8 @@ QD_CHANNEL_DEPOLARIZING, QD_CHANNEL_DEPHASING, QD_CHANNEL_AMPLITUDE_DAMPING = 0,
 QD_OP_GATE, QD_OP_CHANNEL = 0, 1
 QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
- QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID) = range(10)
+ QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID,
+ QD_TUNE_BATCH_FUSE) = range(11)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -185,6 +186,8 @@ _SIGS = {
     "qd_tune_load": (C.c_int, [C.c_char_p]),
     "qd_tune_save": (C.c_int, [C.c_char_p]),
     "qd_batch_autotune": (C.c_int, [_P, C.POINTER(_Gate)]),
+    "qd_batch_apply_layers": (C.c_int, [_P, C.POINTER(_Gate), C.c_int32, C.c_int32]),
+    "qd_batch_autotune_layers": (C.c_int, [_P, C.POINTER(_Gate), C.c_int32]),
     "qd_stream_copy": (C.c_int, [_P, _P, C.c_int64, _P]),
 }
 
@@ -853,6 +856,15 @@ def qd_batch_reset(b: int):
 def qd_batch_apply_layer(b: int, gates):
     """gates: a GateArray with one slot per circuit."""
     _check(load().qd_batch_apply_layer(_P(b), gates.arr))
+
+
+def qd_batch_apply_layers(b: int, gates, nlayers: int, width: int = 0):
+    """gates: a GateArray of nlayers x ncirc slots (layer-major); width 0 = the tuned fusion width."""
+    _check(load().qd_batch_apply_layers(_P(b), gates.arr, int(nlayers), int(width)))
+
+
+def qd_batch_autotune_layers(b: int, gates, nlayers: int):
+    _check(load().qd_batch_autotune_layers(_P(b), gates.arr, int(nlayers)))
 
 
 def qd_batch_capture(b: int, on: bool):

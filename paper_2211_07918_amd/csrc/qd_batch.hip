@@ -17,23 +17,27 @@
 
 namespace qd {
 
-constexpr int kBatchMaxDim = 8;
-constexpr int kBatchGroups = 3;
+constexpr int kBatchMaxDim = 8;     // target dimension of a gate given to a layer
+constexpr int kBatchMaxTargets = 4; // targets of a fused operation (its union of qudits)
+constexpr int kBatchMaxSlice = 16;  // amplitudes per slice (d_T) of an operation
+constexpr int kBatchGroups = kBatchMaxTargets + 1;
+constexpr int kBatchMaxFuse = 8;    // gates composed into one operation
 
 struct BatchDesc {
   int64_t off;                      // arena offset of the circuit's state (amplitudes)
   int64_t base;                     // control offset inside the state
-  int64_t st;                       // target stride
+  int64_t st;                       // target stride of a one-target operation, 0 for a fused one
   uint32_t nwork;                   // active slices
   uint32_t tile0;                   // first global tile of this circuit
-  int32_t dt;                       // target dimension, 0 = no gate in this layer
+  int32_t dt;                       // slice size d_T, 0 = nothing for this circuit in this launch
   int32_t ng;                       // slice-map groups
-  uint32_t uoff;                    // offset of U in the layer's value pool
+  uint32_t uoff;                    // offset of U in the launch's value pool
   uint32_t pad;
   uint32_t gdim[kBatchGroups];
-  uint32_t pad2;
+  uint32_t pad2[kBatchGroups & 1 ? 1 : 2];
   Magic32 gmag[kBatchGroups];
   int64_t gstride[kBatchGroups];
+  int64_t yoff[kBatchMaxSlice];     // offset of local index y inside a slice (fused operations)
 };
 
 template <typename R>
@@ -50,11 +54,13 @@ template <typename R> struct CxB;
 template <> struct CxB<double> { using T = double2; };
 template <> struct CxB<float> { using T = float2; };
 
+// NG: the most groups the descriptor can have (one target and one control leave at most 3 runs)
+template <int NG>
 __device__ __forceinline__ int64_t bd_offset(const BatchDesc& d, uint32_t idx) {
   int64_t off = d.base;
   uint32_t rem = idx;
 #pragma unroll
-  for (int g = 0; g < kBatchGroups; ++g) {
+  for (int g = 0; g < NG; ++g) {
     if (g < d.ng) {
       const uint32_t q = (g + 1 < d.ng) ? magic_div(rem, d.gmag[g]) : 0u;
       off += int64_t(rem - q * d.gdim[g]) * d.gstride[g];
@@ -74,7 +80,8 @@ constexpr int kBatchMaxSpt = 8;
 #define QD_BATCH_ST(p, v) (*(p) = (v))
 #endif
 
-template <typename R, int DT>
+// FUSED: slice offsets from the descriptor's table; else y times the one target's stride
+template <typename R, int DT, bool FUSED>
 __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDesc& d, uint32_t j0, uint32_t j1) {
   using C = typename CxB<R>::T;
   constexpr int KB = (16 / DT) < 1 ? 1 : ((16 / DT) > kBatchMaxSpt ? kBatchMaxSpt : (16 / DT));
@@ -86,10 +93,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const uint32_t j = j0 + threadIdx.x + uint32_t(k0 + k) * blockDim.x;
-      b[k] = (k0 + k < int(a.spt) && j < j1) ? bd_offset(d, j) : -1;
+      b[k] = (k0 + k < int(a.spt) && j < j1) ? bd_offset<FUSED ? kBatchGroups : 3>(d, j) : -1;
       if (b[k] >= 0) {
 #pragma unroll
-        for (int y = 0; y < DT; ++y) x[k][y] = QD_BATCH_LD(psi + (b[k] + y * d.st));
+        for (int y = 0; y < DT; ++y) x[k][y] = QD_BATCH_LD(psi + (b[k] + (FUSED ? d.yoff[y] : y * d.st)));
       }
     }
 #pragma unroll
@@ -109,13 +116,15 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
         C yv;
         yv.x = re;
         yv.y = im;
-        QD_BATCH_ST(psi + (b[k] + r * d.st), yv);
+        QD_BATCH_ST(psi + (b[k] + (FUSED ? d.yoff[r] : r * d.st)), yv);
       }
     }
   }
 }
 
-template <typename R>
+// MAXDT: the largest fused slice this variant handles; a launch without fused operations takes the
+// variant with no fused case at all
+template <typename R, int MAXDT>
 __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
   const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
@@ -135,14 +144,30 @@ __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
     const BatchDesc& d = a.desc[c];
     const uint32_t j0 = (t - d.tile0) * tile_slices;
     const uint32_t j1 = min(d.nwork, j0 + tile_slices);
+    if (d.st) {
+      switch (d.dt) {
+        case 2: batch_tile<R, 2, false>(a, d, j0, j1); break;
+        case 3: batch_tile<R, 3, false>(a, d, j0, j1); break;
+        case 4: batch_tile<R, 4, false>(a, d, j0, j1); break;
+        case 5: batch_tile<R, 5, false>(a, d, j0, j1); break;
+        case 6: batch_tile<R, 6, false>(a, d, j0, j1); break;
+        case 7: batch_tile<R, 7, false>(a, d, j0, j1); break;
+        case 8: batch_tile<R, 8, false>(a, d, j0, j1); break;
+        default: break;
+      }
+      continue;
+    }
     switch (d.dt) {
-      case 2: batch_tile<R, 2>(a, d, j0, j1); break;
-      case 3: batch_tile<R, 3>(a, d, j0, j1); break;
-      case 4: batch_tile<R, 4>(a, d, j0, j1); break;
-      case 5: batch_tile<R, 5>(a, d, j0, j1); break;
-      case 6: batch_tile<R, 6>(a, d, j0, j1); break;
-      case 7: batch_tile<R, 7>(a, d, j0, j1); break;
-      case 8: batch_tile<R, 8>(a, d, j0, j1); break;
+      case 2: if constexpr (MAXDT >= 2) batch_tile<R, 2, true>(a, d, j0, j1); break;
+      case 3: if constexpr (MAXDT >= 3) batch_tile<R, 3, true>(a, d, j0, j1); break;
+      case 4: if constexpr (MAXDT >= 4) batch_tile<R, 4, true>(a, d, j0, j1); break;
+      case 5: if constexpr (MAXDT >= 5) batch_tile<R, 5, true>(a, d, j0, j1); break;
+      case 6: if constexpr (MAXDT >= 6) batch_tile<R, 6, true>(a, d, j0, j1); break;
+      case 7: if constexpr (MAXDT >= 7) batch_tile<R, 7, true>(a, d, j0, j1); break;
+      case 8: if constexpr (MAXDT >= 8) batch_tile<R, 8, true>(a, d, j0, j1); break;
+      case 9: if constexpr (MAXDT >= 9) batch_tile<R, 9, true>(a, d, j0, j1); break;
+      case 12: if constexpr (MAXDT >= 12) batch_tile<R, 12, true>(a, d, j0, j1); break;
+      case 16: if constexpr (MAXDT >= 16) batch_tile<R, 16, true>(a, d, j0, j1); break;
       default: break;
     }
   }
@@ -196,8 +221,8 @@ struct qd_batch {
 namespace qd {
 
 template <typename R>
-static void* batch_kernel_ptr() {
-  return reinterpret_cast<void*>(k_batch_layer<R>);
+static void* batch_kernel_ptr(int maxdt) {
+  return maxdt == 0 ? reinterpret_cast<void*>(k_batch_layer<R, 0>) : reinterpret_cast<void*>(k_batch_layer<R, 16>);
 }
 
 static void free_graph(qd_batch* b) {
@@ -209,6 +234,16 @@ static void free_graph(qd_batch* b) {
   for (void* p : b->layer_bufs) (void)hipFree(p);
   b->layer_bufs.clear();
   b->layer_args.clear();
+}
+
+// exchange the recording state (graph, executable, owned layer buffers) of two batches
+static void swap_graphs(qd_batch* a, qd_batch* b) {
+  std::swap(a->capturing, b->capturing);
+  std::swap(a->graph, b->graph);
+  std::swap(a->exec, b->exec);
+  std::swap(a->last, b->last);
+  std::swap(a->layer_bufs, b->layer_bufs);
+  std::swap(a->layer_args, b->layer_args);
 }
 
 static int batch_reset(qd_batch* b) {
@@ -226,10 +261,23 @@ static int batch_reset(qd_batch* b) {
   return QD_OK;
 }
 
-// Host: descriptors and U pool of one layer; returns the total tile count.
+// One circuit's operation in a launch: up to kBatchMaxTargets targets (first most significant in
+// U's local index), at most one control, U of d_T x d_T (FP64, interleaved). k = 0: nothing.
+struct BatchOp {
+  int k = 0;
+  int32_t t[kBatchMaxTargets] = {};
+  int m = 0;
+  int32_t c = 0, v = 0;
+  std::vector<double> U;
+};
+
+static bool slice_supported(int dT) { return (dT >= 2 && dT <= 9) || dT == 12 || dT == 16; }
+
+// Host: descriptors and U pool of one launch; returns the total tile count.
 template <typename R>
-static int build_layer(qd_batch* b, const qd_gate* gates, std::vector<BatchDesc>* desc, std::vector<R>* pool,
-                       uint32_t* ntiles) {
+static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector<BatchDesc>* desc,
+                       std::vector<R>* pool, uint32_t* ntiles, int* maxdt) {
+  *maxdt = 0;
   const uint32_t nc = uint32_t(b->regs.size());
   const TuneParams& tp = tune();
   const uint64_t tile_slices = uint64_t(tp.batch_block) * tp.batch_spt;
@@ -241,20 +289,19 @@ static int build_layer(qd_batch* b, const qd_gate* gates, std::vector<BatchDesc>
     BatchDesc& d = (*desc)[c];
     d.off = b->offs[c];
     d.tile0 = uint32_t(tiles);
-    const qd_gate& G = gates[c];
-    if (G.k == 0) continue;
-    if (G.k != 1 || G.m > 1) return fail(QD_EINVAL, "batched layers take one target and at most one control (circuit " + std::to_string(c) + ")");
-    int rc = validate_gate(r, G.targets, G.k, G.controls, G.control_values, G.m, G.U, 0);
-    if (rc) return fail(rc, "circuit " + std::to_string(c) + ": " + qd_last_error());
-    const int t = G.targets[0];
-    const int dt = r.dims[t];
-    if (dt > kBatchMaxDim) return fail(QD_EINVAL, "batched layers support target dimensions up to 8");
+    const BatchOp& o = ops[c];
+    if (o.k == 0) continue;
     int role[QD_MAX_QUDITS] = {};
-    role[t] = 1;
+    int dT = 1;
+    for (int j = 0; j < o.k; ++j) {
+      role[o.t[j]] = 1;
+      dT *= r.dims[o.t[j]];
+    }
+    if (!slice_supported(dT)) return fail(QD_EINVAL, "internal: unsupported batched slice size");
     int64_t base = 0;
-    if (G.m == 1) {
-      role[G.controls[0]] = 1;
-      base = int64_t(G.control_values[0]) * r.strides[G.controls[0]];
+    if (o.m == 1) {
+      role[o.c] = 1;
+      base = int64_t(o.v) * r.strides[o.c];
     }
     std::vector<Group> g = make_groups(r, role, nullptr, 0, r.n);
     if (int(g.size()) > kBatchGroups) return fail(QD_EINVAL, "internal: too many groups");
@@ -267,11 +314,22 @@ static int build_layer(qd_batch* b, const qd_gate* gates, std::vector<BatchDesc>
     }
     d.ng = int32_t(g.size());
     d.base = base;
-    d.st = r.strides[t];
-    d.dt = dt;
+    for (int y = 0; y < dT; ++y) {   // offset of local index y: its target digits times their strides
+      int rest = y;
+      int64_t off = 0;
+      for (int j = o.k - 1; j >= 0; --j) {
+        const int dj = r.dims[o.t[j]];
+        off += int64_t(rest % dj) * r.strides[o.t[j]];
+        rest /= dj;
+      }
+      d.yoff[y] = off;
+    }
+    d.dt = dT;
+    d.st = o.k == 1 ? r.strides[o.t[0]] : 0;
+    *maxdt = std::max(*maxdt, o.k == 1 ? 0 : dT);
     d.nwork = uint32_t(nwork);
     d.uoff = uint32_t(pool->size());
-    for (int i = 0; i < 2 * dt * dt; ++i) pool->push_back(R(G.U[i]));
+    for (int i = 0; i < 2 * dT * dT; ++i) pool->push_back(R(o.U[size_t(i)]));
     tiles += (nwork + tile_slices - 1) / tile_slices;
     if (tiles > 0xFFFFFFF0ull) return fail(QD_EOVERFLOW, "too many tiles in one layer");
   }
@@ -279,12 +337,136 @@ static int build_layer(qd_batch* b, const qd_gate* gates, std::vector<BatchDesc>
   return QD_OK;
 }
 
+// A layer's gate for circuit c, validated (one target of dimension <= 8, at most one control).
+static int layer_gate(const qd_batch* b, uint32_t c, const qd_gate& G) {
+  if (G.k == 0) return QD_OK;
+  if (G.k != 1 || G.m > 1) return fail(QD_EINVAL, "batched layers take one target and at most one control (circuit " + std::to_string(c) + ")");
+  const Register& r = b->regs[c];
+  int rc = validate_gate(r, G.targets, G.k, G.controls, G.control_values, G.m, G.U, 0);
+  if (rc) return fail(rc, "circuit " + std::to_string(c) + ": " + qd_last_error());
+  if (r.dims[G.targets[0]] > kBatchMaxDim) return fail(QD_EINVAL, "batched layers support target dimensions up to 8");
+  return QD_OK;
+}
+
+static BatchOp op_of(const qd_batch* b, uint32_t c, const qd_gate& G) {
+  BatchOp o;
+  if (G.k == 0) return o;
+  const int dt = b->regs[c].dims[G.targets[0]];
+  o.k = 1;
+  o.t[0] = G.targets[0];
+  if (G.m == 1) {
+    o.m = 1;
+    o.c = G.controls[0];
+    o.v = G.control_values[0];
+  }
+  o.U.assign(G.U, G.U + 2 * size_t(dt) * dt);
+  return o;
+}
+
+// The union Q of the gates' qudits (targets and controls, ascending) and its dimension d_Q; false
+// when it does not fit one slice.
+static bool gate_union(const Register& r, const qd_gate* const* gs, int w, int* Q, int* nq_out, int* dQ_out) {
+  int nq = 0;
+  for (int i = 0; i < w; ++i) {
+    Q[nq++] = gs[i]->targets[0];
+    if (gs[i]->m == 1) Q[nq++] = gs[i]->controls[0];
+  }
+  std::sort(Q, Q + nq);
+  nq = int(std::unique(Q, Q + nq) - Q);
+  if (nq > kBatchMaxTargets) return false;
+  int dQ = 1;
+  for (int j = 0; j < nq; ++j) dQ *= r.dims[Q[j]];
+  *nq_out = nq;
+  *dQ_out = dQ;
+  return slice_supported(dQ);
+}
+
+// The gates gs[0..w) of one circuit composed on the union Q of their qudits (ascending, first most
+// significant): M = G_{w-1} ... G_0 in FP64, each G_i the gate embedded on Q (U where its control
+// holds its value, the identity elsewhere), applied to the columns of M one target slice at a time.
+// False when Q has more than kBatchMaxTargets qudits or its dimension is not a supported slice size.
+static bool compose_ops(const Register& r, const qd_gate* const* gs, int w, BatchOp* out) {
+  int Q[2 * kBatchMaxFuse];
+  int nq = 0, dQ = 0;
+  if (!gate_union(r, gs, w, Q, &nq, &dQ)) return false;
+  auto pos = [&](int q) { return int(std::find(Q, Q + nq, q) - Q); };
+  int wt[kBatchMaxTargets];   // weight of each Q digit in the local index
+  wt[nq - 1] = 1;
+  for (int j = nq - 2; j >= 0; --j) wt[j] = wt[j + 1] * r.dims[Q[j + 1]];
+  std::vector<double> M(2 * size_t(dQ) * dQ, 0.0);
+  for (int i = 0; i < dQ; ++i) M[2 * (size_t(i) * dQ + i)] = 1.0;
+  double col[2 * kBatchMaxDim];
+  for (int i = 0; i < w; ++i) {
+    const qd_gate& g = *gs[i];
+    const int t = pos(g.targets[0]), dt = r.dims[g.targets[0]], wt_t = wt[t];
+    const int cpos = g.m == 1 ? pos(g.controls[0]) : -1;
+    for (int x0 = 0; x0 < dQ; ++x0) {        // x0: local index whose target digit is 0
+      if ((x0 / wt_t) % dt != 0) continue;
+      if (cpos >= 0 && (x0 / wt[cpos]) % r.dims[g.controls[0]] != g.control_values[0]) continue;
+      for (int bb = 0; bb < dQ; ++bb) {      // rows x0 + y wt_t of column bb <- U times them
+        for (int y = 0; y < dt; ++y) {
+          const size_t e = 2 * (size_t(x0 + y * wt_t) * dQ + bb);
+          col[2 * y] = M[e];
+          col[2 * y + 1] = M[e + 1];
+        }
+        for (int y = 0; y < dt; ++y) {
+          double re = 0.0, im = 0.0;
+          for (int x = 0; x < dt; ++x) {
+            const double ur = g.U[2 * (y * dt + x)], ui = g.U[2 * (y * dt + x) + 1];
+            re += ur * col[2 * x] - ui * col[2 * x + 1];
+            im += ur * col[2 * x + 1] + ui * col[2 * x];
+          }
+          const size_t e = 2 * (size_t(x0 + y * wt_t) * dQ + bb);
+          M[e] = re;
+          M[e + 1] = im;
+        }
+      }
+    }
+  }
+  out->k = nq;
+  for (int j = 0; j < nq; ++j) out->t[j] = Q[j];
+  out->m = 0;
+  out->U = std::move(M);
+  return true;
+}
+
+// The next block of circuit c's gates, from layer *cursor on (empty slots skipped): consecutive
+// gates while the block has at most W of them and they compose on at most kBatchMaxTargets qudits
+// with a supported slice size; a block of one gate stays that gate. *cursor moves past the block;
+// out->k == 0 when the circuit has no gate left.
+static void next_block(const qd_batch* b, uint32_t c, const qd_gate* gates, int32_t nlayers, int W,
+                       int32_t* cursor, BatchOp* out) {
+  const uint32_t nc = uint32_t(b->regs.size());
+  const Register& r = b->regs[c];
+  const qd_gate* cur[kBatchMaxFuse];
+  int n = 0;
+  int32_t l = *cursor;
+  for (; l < nlayers; ++l) {
+    const qd_gate& G = gates[size_t(l) * nc + c];
+    if (G.k == 0) continue;
+    if (n == 0) {
+      cur[n++] = &G;
+      continue;
+    }
+    if (n == W) break;
+    cur[n] = &G;
+    int Q[2 * kBatchMaxFuse], nq = 0, dQ = 0;
+    if (!gate_union(r, cur, n + 1, Q, &nq, &dQ)) break;
+    ++n;
+  }
+  *cursor = l;
+  *out = BatchOp();
+  if (n == 1) *out = op_of(b, c, *cur[0]);
+  else if (n > 1) (void)compose_ops(r, cur, n, out);   // fits: checked as the block grew
+}
+
 template <typename R>
-static int apply_layer_t(qd_batch* b, const qd_gate* gates) {
+static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   std::vector<BatchDesc> desc;
   std::vector<R> pool;
   uint32_t ntiles = 0;
-  int rc = build_layer<R>(b, gates, &desc, &pool, &ntiles);
+  int maxdt = 0;
+  int rc = build_layer<R>(b, ops, &desc, &pool, &ntiles, &maxdt);
   if (rc) return rc;
   const size_t dbytes = desc.size() * sizeof(BatchDesc);
   const size_t pbytes = std::max<size_t>(pool.size(), 1) * sizeof(R);
@@ -312,7 +494,10 @@ static int apply_layer_t(qd_batch* b, const qd_gate* gates) {
     if (rc) return rc;
     a.desc = reinterpret_cast<const BatchDesc*>(dev_blob);
     a.upool = reinterpret_cast<const R*>(static_cast<unsigned char*>(dev_blob) + dpad);
-    hipLaunchKernelGGL((k_batch_layer<R>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
+    if (maxdt == 0)
+      hipLaunchKernelGGL((k_batch_layer<R, 0>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
+    else
+      hipLaunchKernelGGL((k_batch_layer<R, 16>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
     QD_HIP(hipGetLastError());
     return QD_OK;
   }
@@ -330,7 +515,7 @@ static int apply_layer_t(qd_batch* b, const qd_gate* gates) {
   hipKernelNodeParams kp{};
   kp.blockDim = dim3(tp.batch_block);
   kp.gridDim = dim3(grid);
-  kp.func = batch_kernel_ptr<R>();
+  kp.func = batch_kernel_ptr<R>(maxdt);
   kp.kernelParams = kargs;
   kp.sharedMemBytes = 0;
   kp.extra = nullptr;
@@ -408,7 +593,41 @@ int qd_batch_reset(qd_batch* b) {
 
 int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates) {
   if (!b || !gates) return fail(QD_EINVAL, "null argument");
-  return b->prec == QD_C128 ? apply_layer_t<double>(b, gates) : apply_layer_t<float>(b, gates);
+  const uint32_t nc = uint32_t(b->regs.size());
+  std::vector<BatchOp> ops(nc);
+  for (uint32_t c = 0; c < nc; ++c) {
+    int rc = layer_gate(b, c, gates[c]);
+    if (rc) return rc;
+    ops[c] = op_of(b, c, gates[c]);
+  }
+  return b->prec == QD_C128 ? apply_layer_t<double>(b, ops) : apply_layer_t<float>(b, ops);
+}
+
+int qd_batch_apply_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, int32_t width) {
+  if (!b || (nlayers > 0 && !gates)) return fail(QD_EINVAL, "null argument");
+  if (nlayers < 0 || width < 0 || width > kBatchMaxFuse) return fail(QD_EINVAL, "bad layer count or fusion width (0..8)");
+  const int W = width ? width : tune().batch_fuse;
+  const uint32_t nc = uint32_t(b->regs.size());
+  for (int32_t l = 0; l < nlayers; ++l)
+    for (uint32_t c = 0; c < nc; ++c) {
+      int rc = layer_gate(b, c, gates[size_t(l) * nc + c]);
+      if (rc) return rc;
+    }
+  // launch i holds every circuit's i-th block; circuits are independent, so a circuit whose gates
+  // composed into fewer blocks simply has no operation in the later launches
+  std::vector<int32_t> cursor(nc, 0);
+  std::vector<BatchOp> ops(nc);
+  for (;;) {
+    bool any = false;
+    for (uint32_t c = 0; c < nc; ++c) {
+      next_block(b, c, gates, nlayers, W, &cursor[c], &ops[c]);
+      any = any || ops[c].k != 0;
+    }
+    if (!any) break;
+    int rc = b->prec == QD_C128 ? apply_layer_t<double>(b, ops) : apply_layer_t<float>(b, ops);
+    if (rc) return rc;
+  }
+  return QD_OK;
 }
 
 int qd_batch_capture(qd_batch* b, int32_t on) {
@@ -487,6 +706,58 @@ int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
   if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e, "batch autotune");
   if (e2 != hipSuccess) return hip_fail(e2, "batch autotune restore");
+  return QD_OK;
+}
+
+int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers) {
+  if (!b || !gates || nlayers < 1) return fail(QD_EINVAL, "null argument or no layers");
+  if (b->capturing) return fail(QD_EINVAL, "cannot tune while recording");
+  const size_t bytes = size_t(b->total) * amp_bytes(b->prec);
+  void* save = nullptr;
+  QD_HIP(hipMalloc(&save, bytes));
+  hipError_t e = hipMemcpyAsync(save, b->arena, bytes, hipMemcpyDeviceToDevice, b->stream);
+  // each width is recorded into a graph of the tuner's own (the composition on the host happens
+  // while recording, outside the timed replays); the caller's recorded graph is put aside meanwhile
+  qd_batch mine;
+  swap_graphs(b, &mine);
+  TuneParams& tp = tune();
+  const int old = tp.batch_fuse;
+  int best_w = old, rc = QD_OK;
+  float best = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int w : {1, 2, 3, 4, 6, 8}) {
+    if (rc || e != hipSuccess) break;
+    rc = qd_batch_capture(b, 1);
+    if (!rc) rc = qd_batch_apply_layers(b, gates, nlayers, w);
+    if (b->capturing) {
+      const int rc2 = qd_batch_capture(b, 0);
+      if (!rc) rc = rc2;
+    }
+    if (!rc) rc = qd_batch_replay(b);   // warm-up
+    if (!rc) e = hipEventRecord(e0, b->stream);
+    for (int i = 0; i < 2 && !rc && e == hipSuccess; ++i) rc = qd_batch_replay(b);
+    if (!rc && e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (!rc && e == hipSuccess && ms < best) {
+      best = ms;
+      best_w = w;
+    }
+  }
+  tp.batch_fuse = (rc || e != hipSuccess) ? old : best_w;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  hipError_t e2 = hipMemcpyAsync(b->arena, save, bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(b->stream);
+  free_graph(b);
+  swap_graphs(b, &mine);
+  (void)hipFree(save);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "batch fusion autotune");
+  if (e2 != hipSuccess) return hip_fail(e2, "batch fusion autotune restore");
   return QD_OK;
 }
 

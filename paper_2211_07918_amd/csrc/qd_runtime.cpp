@@ -638,6 +638,10 @@ int qd_tune_set(int32_t param, int32_t value) {
       if (value > 64) return fail(QD_EINVAL, "workgroups per compute unit must be 1..64");
       t.batch_wpc = blk(value, def.batch_wpc);
       return QD_OK;
+    case QD_TUNE_BATCH_FUSE:
+      if (value > 8) return fail(QD_EINVAL, "fusion width must be 1..8");
+      t.batch_fuse = blk(value, def.batch_fuse);
+      return QD_OK;
     default:
       return fail(QD_EINVAL, "unknown tuning parameter");
   }
@@ -657,6 +661,7 @@ int qd_tune_get(int32_t param, int32_t* value) {
     case QD_TUNE_FUSED_COLS: *value = t.fused_cols; return QD_OK;
     case QD_TUNE_RUN_MIN: *value = t.run_min; return QD_OK;
     case QD_TUNE_BATCH_GRID: *value = t.batch_wpc; return QD_OK;
+    case QD_TUNE_BATCH_FUSE: *value = t.batch_fuse; return QD_OK;
     default: return fail(QD_EINVAL, "unknown tuning parameter");
   }
 }

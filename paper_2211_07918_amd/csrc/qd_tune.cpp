@@ -66,8 +66,8 @@ static int write_table(const char* path) {
       first = false;
     }
   const TuneParams& tp = tune();
-  std::fprintf(f, "%s{\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d}\n]\n", first ? "" : ",\n",
-               tp.batch_block, tp.batch_spt, tp.batch_wpc);
+  std::fprintf(f, "%s{\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d}\n]\n",
+               first ? "" : ",\n", tp.batch_block, tp.batch_spt, tp.batch_wpc, tp.batch_fuse);
   std::fclose(f);
   return QD_OK;
 }
@@ -132,7 +132,7 @@ int qd_tune_load(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(QD_EINVAL, std::string("cannot read ") + path);
   TuneEntry tab[2][kStrideBuckets] = {};
-  int batch_block = 0, batch_spt = 0, batch_grid = 0, n = 0;
+  int batch_block = 0, batch_spt = 0, batch_grid = 0, batch_fuse = 0, n = 0;
   char line[512];
   while (std::fgets(line, sizeof(line), f)) {
     int p, b, tiled, block, spt, te;
@@ -145,10 +145,11 @@ int qd_tune_load(const char* path) {
       }
       tab[p][b] = TuneEntry{1, tiled ? 1 : 0, block, spt, te};
       ++n;
-    } else if (std::sscanf(line, " {\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d}", &batch_block,
-                           &batch_spt, &batch_grid) >= 2) {
+    } else if (std::sscanf(line, " {\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d}",
+                           &batch_block, &batch_spt, &batch_grid, &batch_fuse) >= 2) {
       if ((batch_block != 64 && batch_block != 128 && batch_block != 192 && batch_block != 256) ||
-          (batch_spt != 1 && batch_spt != 2 && batch_spt != 4 && batch_spt != 8) || batch_grid < 0 || batch_grid > 64) {
+          (batch_spt != 1 && batch_spt != 2 && batch_spt != 4 && batch_spt != 8) || batch_grid < 0 || batch_grid > 64 ||
+          batch_fuse < 0 || batch_fuse > 8) {
         std::fclose(f);
         return fail(QD_EINVAL, "batch tuning entry out of range");
       }
@@ -164,6 +165,7 @@ int qd_tune_load(const char* path) {
     tp.batch_block = batch_block;
     tp.batch_spt = batch_spt;
     if (batch_grid) tp.batch_wpc = batch_grid;
+    if (batch_fuse) tp.batch_fuse = batch_fuse;
   }
   return QD_OK;
 }

@@ -183,3 +183,119 @@ def test_full_4096_circuits(stream):
             assert fidelity_loss(O.run_circuit(c), psi) <= 1e-6, i
         plain = run_gpu(c, Q.QD_C64, stream)
         assert max_abs(plain, psi) <= 4 * 100 * 4 * U24, i
+
+
+def all_layers(circs):
+    """Every layer as one layer-major GateArray (empty slots past a circuit's end)."""
+    L = max(len(c.gates) for c in circs)
+    nc = len(circs)
+    flat = [circs[i].gates[l] if l < len(circs[i].gates) else None for l in range(L) for i in range(nc)]
+    return Q.GateArray(flat, lambda j: circs[j % nc].dims), L
+
+
+@pytest.mark.parametrize("width", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_fused_layers_vs_oracle(stream, width, prec):
+    """Gates composed per circuit into blocks of up to `width` give the oracle's states; the batch
+    holds circuits whose gates compose and circuits that keep one gate per block (a radix-8
+    controlled Haar gate, qutrit controlled shifts), and circuits of different lengths."""
+    circs = small_batch(40, 23, seed=81)
+    for i in (3, 10, 17):                       # shorter circuits: empty slots in the last layers
+        circs[i] = C.Circuit(circs[i].dims, circs[i].gates[:5 + i])
+    ga, L = all_layers(circs)
+    b = Q.qd_batch_create([c.dims for c in circs], prec, stream)
+    try:
+        Q.qd_batch_apply_layers(b, ga, L, width)
+        states = split(Q.qd_batch_download(b, np.complex128 if prec == Q.QD_C128 else np.complex64), b, circs)
+    finally:
+        Q.qd_batch_free(b)
+    for c, psi in zip(circs, states):
+        ref = O.run_circuit(c)
+        if prec == Q.QD_C128:
+            assert max_abs(psi, ref) <= 1e-12
+        else:
+            assert max_abs(psi, ref) <= 4 * len(c.gates) * 16 * U24
+            assert fidelity_loss(ref, psi) <= 1e-6
+
+
+def test_fused_layers_in_a_graph(stream):
+    circs = small_batch(24, 16, seed=82)
+    dims = [c.dims for c in circs]
+    ga, L = all_layers(circs)
+    eager = Q.qd_batch_create(dims, Q.QD_C64, stream)
+    rec = Q.qd_batch_create(dims, Q.QD_C64, stream)
+    try:
+        Q.qd_batch_apply_layers(eager, ga, L, 2)
+        want = Q.qd_batch_download(eager)
+        Q.qd_batch_capture(rec, True)
+        Q.qd_batch_apply_layers(rec, ga, L, 2)
+        Q.qd_batch_capture(rec, False)
+        for rep in range(3):
+            Q.qd_batch_reset(rec)
+            Q.qd_batch_replay(rec)
+            assert np.array_equal(Q.qd_batch_download(rec), want), rep
+            Q.qd_batch_reset(eager)
+            Q.qd_batch_apply_layers(eager, ga, 2, 1)
+    finally:
+        Q.qd_batch_free(eager)
+        Q.qd_batch_free(rec)
+
+
+def test_fusion_autotune_keeps_the_arena_and_graph(stream):
+    """The tuner restores the arena and leaves a graph the caller recorded replayable."""
+    circs = small_batch(16, 8, seed=83)
+    ga, L = all_layers(circs)
+    b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C64, stream)
+    try:
+        Q.qd_batch_capture(b, True)
+        Q.qd_batch_apply_layers(b, ga, 3, 1)
+        Q.qd_batch_capture(b, False)
+        Q.qd_batch_replay(b)
+        before = Q.qd_batch_download(b)
+        Q.qd_batch_autotune_layers(b, ga, L)
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE) in (1, 2, 3, 4, 6, 8)
+        assert np.array_equal(Q.qd_batch_download(b), before)
+        Q.qd_batch_reset(b)
+        Q.qd_batch_replay(b)
+        assert np.array_equal(Q.qd_batch_download(b), before)
+        with pytest.raises(Q.QDError):
+            Q.qd_batch_apply_layers(b, ga, L, 9)
+        with pytest.raises(Q.QDError):
+            Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 9)
+    finally:
+        Q.qd_batch_free(b)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 0)
+
+
+def test_full_4096_circuits_at_the_tuned_width(stream):
+    """The 4096-circuit, 100-layer complex64 batch at the fusion width the tuner picks, recorded as
+    a graph (as the benchmark times it): every register keeps its norm; a seeded sample matches
+    the oracle and the one-by-one plain path within the FP32 bound of 100 passes over slices of
+    up to 16 amplitudes."""
+    circs = C.config4()
+    ga, L = all_layers(circs)
+    b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C64, stream)
+    try:
+        Q.qd_batch_autotune_layers(b, ga, L)
+        print("tuned fusion width", Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE), flush=True)
+        Q.qd_batch_capture(b, True)
+        Q.qd_batch_apply_layers(b, ga, L, 0)
+        Q.qd_batch_capture(b, False)
+        Q.qd_batch_replay(b)
+        arena = Q.qd_batch_download(b)
+    finally:
+        Q.qd_batch_free(b)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 0)
+    offs = np.cumsum([0] + [c.D for c in circs])
+    p = (arena.real.astype(np.float64) ** 2 + arena.imag.astype(np.float64) ** 2)
+    norms = np.add.reduceat(p, offs[:-1])
+    assert np.max(np.abs(norms - 1.0)) <= 4 * 100 * 16 * U24
+    rng = C.seeded_rng(84)
+    sample = sorted(set(rng.choice(len(circs), 12, replace=False).tolist()) | {int(np.argmin(offs[1:] - offs[:-1]))})
+    for i in sample:
+        psi = arena[offs[i]:offs[i + 1]]
+        c = circs[i]
+        if c.D <= 300_000:
+            assert fidelity_loss(O.run_circuit(c), psi) <= 1e-6, i
+        plain = run_gpu(c, Q.QD_C64, stream)
+        assert max_abs(plain, psi) <= 4 * 100 * 16 * U24, i
