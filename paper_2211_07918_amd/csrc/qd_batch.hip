@@ -32,7 +32,7 @@ struct BatchDesc {
   int32_t dt;                       // slice size d_T, 0 = nothing for this circuit in this launch
   int32_t ng;                       // slice-map groups
   uint32_t uoff;                    // offset of U in the launch's value pool
-  uint32_t pad;
+  uint32_t spt;                     // slices per thread of a tile
   uint32_t gdim[kBatchGroups];
   uint32_t pad2[kBatchGroups & 1 ? 1 : 2];
   Magic32 gmag[kBatchGroups];
@@ -45,9 +45,9 @@ struct BatchArgs {
   R* arena;
   const BatchDesc* desc;
   const R* upool;
+  const uint32_t* tmap;             // circuit of each tile
   uint32_t ncirc;
   uint32_t ntiles;
-  uint32_t spt;
 };
 
 template <typename R> struct CxB;
@@ -72,8 +72,10 @@ __device__ __forceinline__ int64_t bd_offset(const BatchDesc& d, uint32_t idx) {
 
 // a thread takes the slices j0 + tid + k blockDim (k < spt <= 8) of the tile, in batches of
 // at most 16 / DT slices whose loads are all issued before the first store (the register peak of
-// the kernel stays that of about 16 amplitudes whatever the gate's dimension)
+// the kernel stays that of about 16 amplitudes whatever the gate's dimension); spt is capped at two
+// such batches, so a wide slice does not make a thread wait on several load round trips in turn
 constexpr int kBatchMaxSpt = 8;
+constexpr int batch_kb(int dt) { return (16 / dt) < 1 ? 1 : ((16 / dt) > kBatchMaxSpt ? kBatchMaxSpt : (16 / dt)); }
 
 #ifndef QD_BATCH_LD
 #define QD_BATCH_LD(p) (*(p))
@@ -81,19 +83,24 @@ constexpr int kBatchMaxSpt = 8;
 #endif
 
 // FUSED: slice offsets from the descriptor's table; else y times the one target's stride
+// d and U sit in LDS (copied per tile): global loads issued after the tile's first stores to the
+// arena could not be served from the scalar cache and would be repeated as vector loads
 template <typename R, int DT, bool FUSED>
-__device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDesc& d, uint32_t j0, uint32_t j1) {
+__device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDesc& d, const R* U, uint32_t j0,
+                                           uint32_t j1) {
   using C = typename CxB<R>::T;
-  constexpr int KB = (16 / DT) < 1 ? 1 : ((16 / DT) > kBatchMaxSpt ? kBatchMaxSpt : (16 / DT));
+  constexpr int KB = batch_kb(DT);
   C* psi = reinterpret_cast<C*>(a.arena) + d.off;
-  const R* U = a.upool + d.uoff;
-  for (int k0 = 0; k0 < int(a.spt); k0 += KB) {
+  const int spt = int(d.spt);
+  for (int k0 = 0; k0 < spt; k0 += KB) {
+    // the LDS values are re-read where used (held in registers they would take hundreds of them)
+    __asm__ volatile("" ::: "memory");
     int64_t b[KB];
     C x[KB][DT];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const uint32_t j = j0 + threadIdx.x + uint32_t(k0 + k) * blockDim.x;
-      b[k] = (k0 + k < int(a.spt) && j < j1) ? bd_offset<FUSED ? kBatchGroups : 3>(d, j) : -1;
+      b[k] = (k0 + k < spt && j < j1) ? bd_offset<FUSED ? kBatchGroups : 3>(d, j) : -1;
       if (b[k] >= 0) {
 #pragma unroll
         for (int y = 0; y < DT; ++y) x[k][y] = QD_BATCH_LD(psi + (b[k] + (FUSED ? d.yoff[y] : y * d.st)));
@@ -104,6 +111,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
       if (b[k] < 0) continue;
 #pragma unroll
       for (int r = 0; r < DT; ++r) {
+        __asm__ volatile("" ::: "memory");
         R re = R(0), im = R(0);
 #pragma unroll
         for (int c = 0; c < DT; ++c) {
@@ -129,45 +137,47 @@ __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
   const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = min(a.ntiles, t0 + per);
-  if (t0 >= t1) return;
-  // first circuit whose tile range holds t0: last c with tile0 <= t0 among circuits with work
-  uint32_t lo = 0, hi = a.ncirc;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (a.desc[mid].tile0 <= t0) lo = mid;
-    else hi = mid;
-  }
-  uint32_t c = lo;
-  const uint32_t tile_slices = blockDim.x * a.spt;
+  __shared__ BatchDesc d;
+  __shared__ R sU[2 * kBatchMaxSlice * kBatchMaxSlice];
+  static_assert(sizeof(BatchDesc) % 8 == 0, "descriptor copied in 8-byte words");
   for (uint32_t t = t0; t < t1; ++t) {
-    while (c + 1 < a.ncirc && a.desc[c + 1].tile0 <= t) ++c;
-    const BatchDesc& d = a.desc[c];
+    const BatchDesc* gd = a.desc + a.tmap[t];
+    __syncthreads();   // the previous tile is done with d and sU
+    if (threadIdx.x < sizeof(BatchDesc) / 8)
+      reinterpret_cast<uint64_t*>(&d)[threadIdx.x] = reinterpret_cast<const uint64_t*>(gd)[threadIdx.x];
+    {
+      const int nu = 2 * gd->dt * gd->dt;
+      const R* gu = a.upool + gd->uoff;
+      for (int i = int(threadIdx.x); i < nu; i += int(blockDim.x)) sU[i] = gu[i];
+    }
+    __syncthreads();
+    const uint32_t tile_slices = blockDim.x * d.spt;
     const uint32_t j0 = (t - d.tile0) * tile_slices;
     const uint32_t j1 = min(d.nwork, j0 + tile_slices);
     if (d.st) {
       switch (d.dt) {
-        case 2: batch_tile<R, 2, false>(a, d, j0, j1); break;
-        case 3: batch_tile<R, 3, false>(a, d, j0, j1); break;
-        case 4: batch_tile<R, 4, false>(a, d, j0, j1); break;
-        case 5: batch_tile<R, 5, false>(a, d, j0, j1); break;
-        case 6: batch_tile<R, 6, false>(a, d, j0, j1); break;
-        case 7: batch_tile<R, 7, false>(a, d, j0, j1); break;
-        case 8: batch_tile<R, 8, false>(a, d, j0, j1); break;
+        case 2: batch_tile<R, 2, false>(a, d, sU, j0, j1); break;
+        case 3: batch_tile<R, 3, false>(a, d, sU, j0, j1); break;
+        case 4: batch_tile<R, 4, false>(a, d, sU, j0, j1); break;
+        case 5: batch_tile<R, 5, false>(a, d, sU, j0, j1); break;
+        case 6: batch_tile<R, 6, false>(a, d, sU, j0, j1); break;
+        case 7: batch_tile<R, 7, false>(a, d, sU, j0, j1); break;
+        case 8: batch_tile<R, 8, false>(a, d, sU, j0, j1); break;
         default: break;
       }
       continue;
     }
     switch (d.dt) {
-      case 2: if constexpr (MAXDT >= 2) batch_tile<R, 2, true>(a, d, j0, j1); break;
-      case 3: if constexpr (MAXDT >= 3) batch_tile<R, 3, true>(a, d, j0, j1); break;
-      case 4: if constexpr (MAXDT >= 4) batch_tile<R, 4, true>(a, d, j0, j1); break;
-      case 5: if constexpr (MAXDT >= 5) batch_tile<R, 5, true>(a, d, j0, j1); break;
-      case 6: if constexpr (MAXDT >= 6) batch_tile<R, 6, true>(a, d, j0, j1); break;
-      case 7: if constexpr (MAXDT >= 7) batch_tile<R, 7, true>(a, d, j0, j1); break;
-      case 8: if constexpr (MAXDT >= 8) batch_tile<R, 8, true>(a, d, j0, j1); break;
-      case 9: if constexpr (MAXDT >= 9) batch_tile<R, 9, true>(a, d, j0, j1); break;
-      case 12: if constexpr (MAXDT >= 12) batch_tile<R, 12, true>(a, d, j0, j1); break;
-      case 16: if constexpr (MAXDT >= 16) batch_tile<R, 16, true>(a, d, j0, j1); break;
+      case 2: if constexpr (MAXDT >= 2) batch_tile<R, 2, true>(a, d, sU, j0, j1); break;
+      case 3: if constexpr (MAXDT >= 3) batch_tile<R, 3, true>(a, d, sU, j0, j1); break;
+      case 4: if constexpr (MAXDT >= 4) batch_tile<R, 4, true>(a, d, sU, j0, j1); break;
+      case 5: if constexpr (MAXDT >= 5) batch_tile<R, 5, true>(a, d, sU, j0, j1); break;
+      case 6: if constexpr (MAXDT >= 6) batch_tile<R, 6, true>(a, d, sU, j0, j1); break;
+      case 7: if constexpr (MAXDT >= 7) batch_tile<R, 7, true>(a, d, sU, j0, j1); break;
+      case 8: if constexpr (MAXDT >= 8) batch_tile<R, 8, true>(a, d, sU, j0, j1); break;
+      case 9: if constexpr (MAXDT >= 9) batch_tile<R, 9, true>(a, d, sU, j0, j1); break;
+      case 12: if constexpr (MAXDT >= 12) batch_tile<R, 12, true>(a, d, sU, j0, j1); break;
+      case 16: if constexpr (MAXDT >= 16) batch_tile<R, 16, true>(a, d, sU, j0, j1); break;
       default: break;
     }
   }
@@ -280,7 +290,6 @@ static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector
   *maxdt = 0;
   const uint32_t nc = uint32_t(b->regs.size());
   const TuneParams& tp = tune();
-  const uint64_t tile_slices = uint64_t(tp.batch_block) * tp.batch_spt;
   desc->assign(nc, BatchDesc{});
   pool->clear();
   uint64_t tiles = 0;
@@ -330,6 +339,8 @@ static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector
     d.nwork = uint32_t(nwork);
     d.uoff = uint32_t(pool->size());
     for (int i = 0; i < 2 * dT * dT; ++i) pool->push_back(R(o.U[size_t(i)]));
+    d.spt = uint32_t(std::min(tp.batch_spt, 2 * batch_kb(dT)));
+    const uint64_t tile_slices = uint64_t(tp.batch_block) * d.spt;
     tiles += (nwork + tile_slices - 1) / tile_slices;
     if (tiles > 0xFFFFFFF0ull) return fail(QD_EOVERFLOW, "too many tiles in one layer");
   }
@@ -471,9 +482,15 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   const size_t dbytes = desc.size() * sizeof(BatchDesc);
   const size_t pbytes = std::max<size_t>(pool.size(), 1) * sizeof(R);
   const size_t dpad = (dbytes + 255) / 256 * 256;
-  std::vector<unsigned char> blob(dpad + pbytes, 0);
+  const size_t ppad = (pbytes + 255) / 256 * 256;
+  std::vector<unsigned char> blob(dpad + ppad + std::max<size_t>(ntiles, 1) * sizeof(uint32_t), 0);
   std::memcpy(blob.data(), desc.data(), dbytes);
   if (!pool.empty()) std::memcpy(blob.data() + dpad, pool.data(), pool.size() * sizeof(R));
+  uint32_t* tmap = reinterpret_cast<uint32_t*>(blob.data() + dpad + ppad);   // tile -> circuit
+  for (uint32_t c = 0; c < uint32_t(desc.size()); ++c) {
+    const uint32_t end = c + 1 < uint32_t(desc.size()) ? desc[c + 1].tile0 : ntiles;
+    for (uint32_t t = desc[c].tile0; t < end; ++t) tmap[t] = c;
+  }
   const TuneParams& tp = tune();
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
@@ -486,7 +503,6 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   a.arena = reinterpret_cast<R*>(b->arena);
   a.ncirc = uint32_t(desc.size());
   a.ntiles = ntiles;
-  a.spt = uint32_t(tp.batch_spt);
   if (!b->capturing) {
     if (ntiles == 0) return QD_OK;
     void* dev_blob = nullptr;
@@ -494,6 +510,7 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
     if (rc) return rc;
     a.desc = reinterpret_cast<const BatchDesc*>(dev_blob);
     a.upool = reinterpret_cast<const R*>(static_cast<unsigned char*>(dev_blob) + dpad);
+    a.tmap = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(dev_blob) + dpad + ppad);
     if (maxdt == 0)
       hipLaunchKernelGGL((k_batch_layer<R, 0>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
     else
@@ -509,6 +526,7 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   if (ntiles == 0) return QD_OK;
   a.desc = reinterpret_cast<const BatchDesc*>(buf);
   a.upool = reinterpret_cast<const R*>(static_cast<unsigned char*>(buf) + dpad);
+  a.tmap = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(buf) + dpad + ppad);
   b->layer_args.emplace_back(sizeof(a));
   std::memcpy(b->layer_args.back().data(), &a, sizeof(a));
   void* kargs[1] = {b->layer_args.back().data()};
