@@ -56,7 +56,10 @@ def parse():
     ap.add_argument("--no-big", action="store_true", help="skip the 20-qutrit (28 + 56 GB) precision run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--extras", default="copy,qft,brick,batch,measure,frontend,sparse,density",
-                    help="comma list of extras: copy, qft, brick, batch")
+                    help="comma list of extras: copy, qft, brick, batch, measure, frontend, sparse, density")
+    ap.add_argument("--batch-no-serial", action="store_true",
+                    help="batched leg: skip the one-by-one comparison (409,600 separate launches), e.g. "
+                         "under a counter profiler")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -571,7 +574,43 @@ def bench_density_cpu(C, seconds):
             "sample": f"{done} operations of the same recipe on 3 qubits + 2 qutrits (D = {D}), NumPy, 1 thread, {dt:.1f} s"}
 
 
-def bench_batch(Q, torch, ncirc=4096):
+_BATCH_SLICES = set(range(2, 10)) | {12, 16}
+
+
+def batch_schedule(circs, W):
+    """Launches and algorithmic bytes (complex64, read + write of every amplitude a pass touches) of
+    qd_batch_apply_layers at fusion width W, by the library's block rule: a circuit's next gates
+    join a block while it has at most W of them and their qudits number at most 4 with a slice
+    size in {2..9, 12, 16}; a one-gate block touches D / d_c amplitudes, a composed one all D."""
+    import numpy as np
+    launches, nbytes = 0, 0
+    for c in circs:
+        blocks, cur, q = 0, [], set()
+        for g in c.gates:
+            u = q | set(g.targets) | set(g.controls)
+            if cur and len(cur) < W and len(u) <= 4 and int(np.prod([c.dims[x] for x in u])) in _BATCH_SLICES:
+                cur.append(g)
+                q = u
+                continue
+            if cur:
+                blocks += 1
+                nbytes += _block_bytes(c, cur)
+            cur, q = [g], set(g.targets) | set(g.controls)
+        if cur:
+            blocks += 1
+            nbytes += _block_bytes(c, cur)
+        launches = max(launches, blocks)
+    return launches, nbytes
+
+
+def _block_bytes(c, gates):
+    import numpy as np
+    if len(gates) > 1 or not gates[0].controls:
+        return 16 * c.D
+    return 16 * c.D // int(np.prod([c.dims[x] for x in gates[0].controls]))
+
+
+def bench_batch(Q, torch, ncirc=4096, serial=True):
     """4096 seeded circuits over uneven registers, 100 layers, complex64, recorded into a hipGraph:
     one persistent launch per layer (fusion width 1) and each circuit's gates composed into
     blocks of up to the autotuned fusion width, against the same gates applied one by one
@@ -612,23 +651,27 @@ def bench_batch(Q, torch, ncirc=4096):
     ms1 = graph_ms(1)
     ms = graph_ms(width) if width != 1 else ms1
     Q.qd_batch_free(b)
-    # one by one: every gate of every circuit through qd_apply_gate on its own state
-    states = [Q.qd_state_init(c.dims, Q.QD_C64, stream) for c in circs]
-    mats = [[(g.targets, g.controls, g.cvals, Q.gate_unitary(g, c.dims)) for g in c.gates] for c in circs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s, m in zip(states, mats):
-        for t, cc, v, U in m:
-            Q.qd_apply_gate(s, t, cc, v, U)
-    torch.cuda.synchronize()
-    one_s = time.perf_counter() - t0
-    for s in states:
-        Q.qd_state_free(s)
+    one_s = None
+    if serial:
+        # one by one: every gate of every circuit through qd_apply_gate on its own state
+        states = [Q.qd_state_init(c.dims, Q.QD_C64, stream) for c in circs]
+        mats = [[(g.targets, g.controls, g.cvals, Q.gate_unitary(g, c.dims)) for g in c.gates] for c in circs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, m in zip(states, mats):
+            for t, cc, v, U in m:
+                Q.qd_apply_gate(s, t, cc, v, U)
+        torch.cuda.synchronize()
+        one_s = time.perf_counter() - t0
+        for s in states:
+            Q.qd_state_free(s)
+    launches, nbytes = batch_schedule(circs, width)
     return {"circuits": ncirc, "layers": L, "sum_D": int(sum(c.D for c in circs)), "graph_ms": ms,
-            "fusion_width": width, "graph_ms_width1": ms1,
+            "fusion_width": width, "graph_ms_width1": ms1, "launches": launches,
+            "algorithmic_bytes": nbytes, "hbm_GBps": nbytes / (ms * 1e-3) / 1e9,
             "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
             "hbm_GBps_width1": 16.0 * upd / (ms1 * 1e-3) / 1e9, "one_by_one_s": one_s,
-            "speedup_vs_one_by_one": one_s / (ms * 1e-3), "tuned_block": block, "tuned_spt": spt,
+            "speedup_vs_one_by_one": one_s / (ms * 1e-3) if one_s else None, "tuned_block": block, "tuned_spt": spt,
             "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU"}
 
 
@@ -714,11 +757,12 @@ def main():
     if "brick" in which and not args.no_big:
         extras["fused_brickwork_20_qutrits"] = bench_fused(Q, torch, C.config3(20, 30), 81, "brick20", warm=False)
     if "batch" in which:
-        extras["batched_4096_circuits"] = bench_batch(Q, torch)
+        extras["batched_4096_circuits"] = bench_batch(Q, torch, serial=not args.batch_no_serial)
         bb = extras["batched_4096_circuits"]
         log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers at fusion width {bb['fusion_width']} "
             f"({bb['graph_ms_width1']:.1f} ms at width 1), {bb['amp_upd_per_s']:.3e} amp-upd/s, "
-            f"x{bb['speedup_vs_one_by_one']:.1f} vs one by one")
+            f"{bb['hbm_GBps']:.0f} GB/s over {bb['launches']} launches"
+            + (f", x{bb['speedup_vs_one_by_one']:.1f} vs one by one" if bb['speedup_vs_one_by_one'] else ""))
     if "frontend" in which:
         fe = bench_frontend(Q)
         extras["frontend_qasm"] = fe
