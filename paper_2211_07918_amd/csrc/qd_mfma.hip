@@ -579,6 +579,9 @@ static int launch_one(const FusedArgs& a, hipStream_t st, int per_cu) {
 
 // Kernel shapes by block dimension B (2B real rows): KPAD = 64 MTW >= 2B.
 //   B <= 32: 1 tile of A per wave; B <= 64: 2; B <= 81: 3 (41 FP32 K steps); B <= 96: 3; B <= 128: 4.
+// Persistent workgroups per CU: as many as registers and LDS hold (4 for B <= 32, 3 for B <= 64, 2
+// above), so that one workgroup's tile copies overlap the others' products; double-buffering the
+// tile in one workgroup measured slower on the 64-wide blocks (it leaves room for two).
 static int variant_of(int B) { return B <= 32 ? 0 : (B <= 64 ? 1 : (B <= 81 ? 2 : (B <= 96 ? 3 : 4))); }
 static int variant_kpad(int v) { return v == 0 ? 64 : (v == 1 ? 128 : (v <= 3 ? 192 : 256)); }
 static int variant_ntiles(int v) { return (v == 2 || v == 3) ? 6 : 4; }
@@ -592,10 +595,10 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
   const bool bf = mode == QD_MODE_BF16X3_MFMA;
   if (a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
     switch (d.variant) {
-      case 0: return bf ? launch_rows<1, 4, 1, 2, true, 2>(a, s->stream, 3)
-                        : launch_rows<1, 4, 1, 16, false, 2>(a, s->stream, 3);
-      case 1: return bf ? launch_rows<2, 4, 1, 4, true, 2>(a, s->stream, 2)
-                        : launch_rows<2, 4, 1, 32, false, 2>(a, s->stream, 2);
+      case 0: return bf ? launch_rows<1, 4, 1, 2, true, 2>(a, s->stream, 4)
+                        : launch_rows<1, 4, 1, 16, false, 2>(a, s->stream, 4);
+      case 1: return bf ? launch_rows<2, 4, 1, 4, true, 2>(a, s->stream, 3)
+                        : launch_rows<2, 4, 1, 32, false, 2>(a, s->stream, 3);
       case 2: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
                         : launch_rows<3, 6, 2, 41, false, 2>(a, s->stream, 2);
       case 3: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
