@@ -109,8 +109,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       if (b[k] < 0) continue;
-#pragma unroll
-      for (int r = 0; r < DT; ++r) {
+      auto row = [&](int r) {
         __asm__ volatile("" ::: "memory");
         R re = R(0), im = R(0);
 #pragma unroll
@@ -125,13 +124,23 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
         yv.x = re;
         yv.y = im;
         QD_BATCH_ST(psi + (b[k] + (FUSED ? d.yoff[r] : r * d.st)), yv);
+      };
+      // composed slices of 6 or more amplitudes keep their rows as a loop: unrolled, the cases of
+      // every slice size that share a launch would overflow the instruction cache
+      if constexpr (FUSED && DT >= 6) {
+#pragma unroll 1
+        for (int r = 0; r < DT; ++r) row(r);
+      } else {
+#pragma unroll
+        for (int r = 0; r < DT; ++r) row(r);
       }
     }
   }
 }
 
-// MAXDT: the largest fused slice this variant handles; a launch without fused operations takes the
-// variant with no fused case at all
+// MAXDT = 0: a launch of one-gate operations only, addressed y times the target's stride; otherwise
+// every operation of the launch (composed ones with slices of up to 16 amplitudes, and one-gate ones)
+// is addressed through its offset table, so the variant holds one set of cases
 template <typename R, int MAXDT>
 __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
   const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
@@ -154,7 +163,7 @@ __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
     const uint32_t tile_slices = blockDim.x * d.spt;
     const uint32_t j0 = (t - d.tile0) * tile_slices;
     const uint32_t j1 = min(d.nwork, j0 + tile_slices);
-    if (d.st) {
+    if constexpr (MAXDT == 0) {
       switch (d.dt) {
         case 2: batch_tile<R, 2, false>(a, d, sU, j0, j1); break;
         case 3: batch_tile<R, 3, false>(a, d, sU, j0, j1); break;
@@ -165,20 +174,20 @@ __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
         case 8: batch_tile<R, 8, false>(a, d, sU, j0, j1); break;
         default: break;
       }
-      continue;
-    }
-    switch (d.dt) {
-      case 2: if constexpr (MAXDT >= 2) batch_tile<R, 2, true>(a, d, sU, j0, j1); break;
-      case 3: if constexpr (MAXDT >= 3) batch_tile<R, 3, true>(a, d, sU, j0, j1); break;
-      case 4: if constexpr (MAXDT >= 4) batch_tile<R, 4, true>(a, d, sU, j0, j1); break;
-      case 5: if constexpr (MAXDT >= 5) batch_tile<R, 5, true>(a, d, sU, j0, j1); break;
-      case 6: if constexpr (MAXDT >= 6) batch_tile<R, 6, true>(a, d, sU, j0, j1); break;
-      case 7: if constexpr (MAXDT >= 7) batch_tile<R, 7, true>(a, d, sU, j0, j1); break;
-      case 8: if constexpr (MAXDT >= 8) batch_tile<R, 8, true>(a, d, sU, j0, j1); break;
-      case 9: if constexpr (MAXDT >= 9) batch_tile<R, 9, true>(a, d, sU, j0, j1); break;
-      case 12: if constexpr (MAXDT >= 12) batch_tile<R, 12, true>(a, d, sU, j0, j1); break;
-      case 16: if constexpr (MAXDT >= 16) batch_tile<R, 16, true>(a, d, sU, j0, j1); break;
-      default: break;
+    } else {
+      switch (d.dt) {
+        case 2: batch_tile<R, 2, true>(a, d, sU, j0, j1); break;
+        case 3: batch_tile<R, 3, true>(a, d, sU, j0, j1); break;
+        case 4: batch_tile<R, 4, true>(a, d, sU, j0, j1); break;
+        case 5: batch_tile<R, 5, true>(a, d, sU, j0, j1); break;
+        case 6: batch_tile<R, 6, true>(a, d, sU, j0, j1); break;
+        case 7: batch_tile<R, 7, true>(a, d, sU, j0, j1); break;
+        case 8: batch_tile<R, 8, true>(a, d, sU, j0, j1); break;
+        case 9: batch_tile<R, 9, true>(a, d, sU, j0, j1); break;
+        case 12: batch_tile<R, 12, true>(a, d, sU, j0, j1); break;
+        case 16: batch_tile<R, 16, true>(a, d, sU, j0, j1); break;
+        default: break;
+      }
     }
   }
 }
