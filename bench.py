@@ -632,6 +632,7 @@ def bench_batch(Q, torch, ncirc=4096, serial=True):
     grid = Q.qd_tune_get(Q.QD_TUNE_BATCH_GRID)
     Q.qd_batch_autotune_layers(b, flat, L)
     width = Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE)
+    spt_cls = (Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_MID), Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_WIDE))
     e0, e1 = _ev(torch)
     reps = 3
 
@@ -672,7 +673,8 @@ def bench_batch(Q, torch, ncirc=4096, serial=True):
             "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
             "hbm_GBps_width1": 16.0 * upd / (ms1 * 1e-3) / 1e9, "one_by_one_s": one_s,
             "speedup_vs_one_by_one": one_s / (ms * 1e-3) if one_s else None, "tuned_block": block, "tuned_spt": spt,
-            "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU"}
+            "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU",
+            "tuned_spt_d5_9": spt_cls[0] or "rule", "tuned_spt_d12_16": spt_cls[1] or "rule"}
 
 
 def host_info():

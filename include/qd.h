@@ -543,8 +543,10 @@ int qd_batch_apply_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, in
 
 /* Fusion-width autotuner: records qd_batch_apply_layers over the given layers into a graph for
  * widths 1, 2, 3, 4, 6 and 8, times replays of each (host composition excluded) and keeps the
- * fastest as QD_TUNE_BATCH_FUSE (saved by qd_tune_save). The arena is saved and restored and a
- * graph the caller recorded is kept. Not allowed while recording. Synchronises. */
+ * fastest as QD_TUNE_BATCH_FUSE; then, at that width, the slices per thread of each wide slice
+ * class (QD_TUNE_BATCH_SPT_MID, then QD_TUNE_BATCH_SPT_WIDE: the rule, 1, 2, 4, 8). All are saved
+ * by qd_tune_save. The arena is saved and restored and a graph the caller recorded is kept. Not
+ * allowed while recording. Synchronises. */
 int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers);
 
 /* on = 1 starts recording layers into a new graph (dropping any previous one); on = 0 ends the
@@ -572,13 +574,15 @@ void qd_batch_free(qd_batch* b);
  * slice columns per fused tile (32, 64, 128), the target stride below which a gate is staged
  * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes) and the workgroups per compute unit of the batched
  * layer kernel (QD_TUNE_BATCH_GRID: 1..63 persistent workgroups walk the tile list; 64 launches one
- * workgroup per tile) and the most gates qd_batch_apply_layers composes into one operation
- * (QD_TUNE_BATCH_FUSE, 1..8). 0 restores the default. Process-wide,
+ * workgroup per tile), the most gates qd_batch_apply_layers composes into one operation
+ * (QD_TUNE_BATCH_FUSE, 1..8) and the slices per thread of batched slices of 5..9 and of 12 or 16
+ * amplitudes (QD_TUNE_BATCH_SPT_MID, QD_TUNE_BATCH_SPT_WIDE: 1, 2, 4 or 8; 0 keeps the rule of two
+ * batches of 16 / d_T slices, at most QD_TUNE_BATCH_SPT). 0 restores the default. Process-wide,
  * host only; QD_EINVAL for an unknown parameter or a value outside its range. */
 enum { QD_TUNE_DIRECT_BLOCK = 0, QD_TUNE_DIRECT_SPT = 1, QD_TUNE_TILE_BLOCK = 2,
        QD_TUNE_TILE_ELEMS = 3, QD_TUNE_DIAG_BLOCK = 4, QD_TUNE_BATCH_BLOCK = 5,
        QD_TUNE_BATCH_SPT = 6, QD_TUNE_FUSED_COLS = 7, QD_TUNE_RUN_MIN = 8, QD_TUNE_BATCH_GRID = 9,
-       QD_TUNE_BATCH_FUSE = 10, QD_TUNE_COUNT = 11 };
+       QD_TUNE_BATCH_FUSE = 10, QD_TUNE_BATCH_SPT_MID = 11, QD_TUNE_BATCH_SPT_WIDE = 12, QD_TUNE_COUNT = 13 };
 int qd_tune_set(int32_t param, int32_t value);
 int qd_tune_get(int32_t param, int32_t* value);
 

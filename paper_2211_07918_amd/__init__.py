@@ -29,7 +29,8 @@ __all__ = [
     "qd_density_apply_ops", "QD_OP_GATE", "QD_OP_CHANNEL",
     "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
-    "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "qd_batch_apply_layers", "qd_batch_autotune_layers",
+    "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "QD_TUNE_BATCH_SPT_MID", "QD_TUNE_BATCH_SPT_WIDE",
+    "qd_batch_apply_layers", "qd_batch_autotune_layers",
     "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "qd_gate_route",
     "qd_version", "qd_last_error", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
@@ -63,7 +64,7 @@ QD_OP_GATE, QD_OP_CHANNEL = 0, 1
 QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
  QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID,
- QD_TUNE_BATCH_FUSE) = range(11)
+ QD_TUNE_BATCH_FUSE, QD_TUNE_BATCH_SPT_MID, QD_TUNE_BATCH_SPT_WIDE) = range(13)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None

@@ -348,7 +348,8 @@ static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector
     d.nwork = uint32_t(nwork);
     d.uoff = uint32_t(pool->size());
     for (int i = 0; i < 2 * dT * dT; ++i) pool->push_back(R(o.U[size_t(i)]));
-    d.spt = uint32_t(std::min(tp.batch_spt, 2 * batch_kb(dT)));
+    const int cls = dT >= 12 ? tp.batch_spt_wide : (dT >= 5 ? tp.batch_spt_mid : 0);   // tuned per slice class
+    d.spt = uint32_t(cls ? cls : std::min(tp.batch_spt, 2 * batch_kb(dT)));
     const uint64_t tile_slices = uint64_t(tp.batch_block) * d.spt;
     tiles += (nwork + tile_slices - 1) / tile_slices;
     if (tiles > 0xFFFFFFF0ull) return fail(QD_EOVERFLOW, "too many tiles in one layer");
@@ -736,6 +737,30 @@ int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
   return QD_OK;
 }
 
+}  // extern "C"
+
+namespace qd {
+// Record the layers at fusion width w into the batch's graph, replay it once, then time two replays.
+static int time_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, int w, hipEvent_t e0, hipEvent_t e1,
+                       float* ms, hipError_t* e) {
+  int rc = qd_batch_capture(b, 1);
+  if (!rc) rc = qd_batch_apply_layers(b, gates, nlayers, w);
+  if (b->capturing) {
+    const int rc2 = qd_batch_capture(b, 0);
+    if (!rc) rc = rc2;
+  }
+  if (!rc) rc = qd_batch_replay(b);   // warm-up
+  if (!rc) *e = hipEventRecord(e0, b->stream);
+  for (int i = 0; i < 2 && !rc && *e == hipSuccess; ++i) rc = qd_batch_replay(b);
+  if (!rc && *e == hipSuccess) *e = hipEventRecord(e1, b->stream);
+  if (!rc && *e == hipSuccess) *e = hipEventSynchronize(e1);
+  if (!rc && *e == hipSuccess) *e = hipEventElapsedTime(ms, e0, e1);
+  return rc;
+}
+}  // namespace qd
+
+extern "C" {
+
 int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers) {
   if (!b || !gates || nlayers < 1) return fail(QD_EINVAL, "null argument or no layers");
   if (b->capturing) return fail(QD_EINVAL, "cannot tune while recording");
@@ -756,25 +781,30 @@ int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers)
   if (e == hipSuccess) e = hipEventCreate(&e1);
   for (int w : {1, 2, 3, 4, 6, 8}) {
     if (rc || e != hipSuccess) break;
-    rc = qd_batch_capture(b, 1);
-    if (!rc) rc = qd_batch_apply_layers(b, gates, nlayers, w);
-    if (b->capturing) {
-      const int rc2 = qd_batch_capture(b, 0);
-      if (!rc) rc = rc2;
-    }
-    if (!rc) rc = qd_batch_replay(b);   // warm-up
-    if (!rc) e = hipEventRecord(e0, b->stream);
-    for (int i = 0; i < 2 && !rc && e == hipSuccess; ++i) rc = qd_batch_replay(b);
-    if (!rc && e == hipSuccess) e = hipEventRecord(e1, b->stream);
-    if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
-    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    rc = time_layers(b, gates, nlayers, w, e0, e1, &ms, &e);
     if (!rc && e == hipSuccess && ms < best) {
       best = ms;
       best_w = w;
     }
   }
   tp.batch_fuse = (rc || e != hipSuccess) ? old : best_w;
+  // then, at that width, slices per thread of the two wide slice classes in turn (0: the rule)
+  for (int* knob : {&tp.batch_spt_mid, &tp.batch_spt_wide}) {
+    const int keep = *knob;
+    int best_v = keep;
+    for (int v : {0, 1, 2, 4, 8}) {
+      if (rc || e != hipSuccess || v == keep) continue;
+      *knob = v;
+      float ms = 0.f;
+      rc = time_layers(b, gates, nlayers, best_w, e0, e1, &ms, &e);
+      if (!rc && e == hipSuccess && ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    *knob = (rc || e != hipSuccess) ? keep : best_v;
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   hipError_t e2 = hipMemcpyAsync(b->arena, save, bytes, hipMemcpyDeviceToDevice, b->stream);

@@ -642,6 +642,12 @@ int qd_tune_set(int32_t param, int32_t value) {
       if (value > 8) return fail(QD_EINVAL, "fusion width must be 1..8");
       t.batch_fuse = blk(value, def.batch_fuse);
       return QD_OK;
+    case QD_TUNE_BATCH_SPT_MID:
+    case QD_TUNE_BATCH_SPT_WIDE:
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(QD_EINVAL, "batch slices per thread must be 0 (the default rule), 1, 2, 4 or 8");
+      (param == QD_TUNE_BATCH_SPT_MID ? t.batch_spt_mid : t.batch_spt_wide) = value;
+      return QD_OK;
     default:
       return fail(QD_EINVAL, "unknown tuning parameter");
   }
@@ -662,6 +668,8 @@ int qd_tune_get(int32_t param, int32_t* value) {
     case QD_TUNE_RUN_MIN: *value = t.run_min; return QD_OK;
     case QD_TUNE_BATCH_GRID: *value = t.batch_wpc; return QD_OK;
     case QD_TUNE_BATCH_FUSE: *value = t.batch_fuse; return QD_OK;
+    case QD_TUNE_BATCH_SPT_MID: *value = t.batch_spt_mid; return QD_OK;
+    case QD_TUNE_BATCH_SPT_WIDE: *value = t.batch_spt_wide; return QD_OK;
     default: return fail(QD_EINVAL, "unknown tuning parameter");
   }
 }

@@ -66,8 +66,11 @@ static int write_table(const char* path) {
       first = false;
     }
   const TuneParams& tp = tune();
-  std::fprintf(f, "%s{\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d}\n]\n",
-               first ? "" : ",\n", tp.batch_block, tp.batch_spt, tp.batch_wpc, tp.batch_fuse);
+  std::fprintf(f,
+               "%s{\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d, "
+               "\"batch_spt_mid\": %d, \"batch_spt_wide\": %d}\n]\n",
+               first ? "" : ",\n", tp.batch_block, tp.batch_spt, tp.batch_wpc, tp.batch_fuse, tp.batch_spt_mid,
+               tp.batch_spt_wide);
   std::fclose(f);
   return QD_OK;
 }
@@ -132,7 +135,7 @@ int qd_tune_load(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(QD_EINVAL, std::string("cannot read ") + path);
   TuneEntry tab[2][kStrideBuckets] = {};
-  int batch_block = 0, batch_spt = 0, batch_grid = 0, batch_fuse = 0, n = 0;
+  int batch_block = 0, batch_spt = 0, batch_grid = 0, batch_fuse = 0, spt_mid = 0, spt_wide = 0, n = 0;
   char line[512];
   while (std::fgets(line, sizeof(line), f)) {
     int p, b, tiled, block, spt, te;
@@ -145,11 +148,14 @@ int qd_tune_load(const char* path) {
       }
       tab[p][b] = TuneEntry{1, tiled ? 1 : 0, block, spt, te};
       ++n;
-    } else if (std::sscanf(line, " {\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d}",
-                           &batch_block, &batch_spt, &batch_grid, &batch_fuse) >= 2) {
+    } else if (std::sscanf(line,
+                           " {\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d, "
+                           "\"batch_spt_mid\": %d, \"batch_spt_wide\": %d}",
+                           &batch_block, &batch_spt, &batch_grid, &batch_fuse, &spt_mid, &spt_wide) >= 2) {
+      auto spt_ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
       if ((batch_block != 64 && batch_block != 128 && batch_block != 192 && batch_block != 256) ||
           (batch_spt != 1 && batch_spt != 2 && batch_spt != 4 && batch_spt != 8) || batch_grid < 0 || batch_grid > 64 ||
-          batch_fuse < 0 || batch_fuse > 8) {
+          batch_fuse < 0 || batch_fuse > 8 || !spt_ok(spt_mid) || !spt_ok(spt_wide)) {
         std::fclose(f);
         return fail(QD_EINVAL, "batch tuning entry out of range");
       }
@@ -166,6 +172,8 @@ int qd_tune_load(const char* path) {
     tp.batch_spt = batch_spt;
     if (batch_grid) tp.batch_wpc = batch_grid;
     if (batch_fuse) tp.batch_fuse = batch_fuse;
+    tp.batch_spt_mid = spt_mid;
+    tp.batch_spt_wide = spt_wide;
   }
   return QD_OK;
 }

@@ -254,6 +254,8 @@ def test_fusion_autotune_keeps_the_arena_and_graph(stream):
         before = Q.qd_batch_download(b)
         Q.qd_batch_autotune_layers(b, ga, L)
         assert Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE) in (1, 2, 3, 4, 6, 8)
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_MID) in (0, 1, 2, 4, 8)
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_WIDE) in (0, 1, 2, 4, 8)
         assert np.array_equal(Q.qd_batch_download(b), before)
         Q.qd_batch_reset(b)
         Q.qd_batch_replay(b)
@@ -264,7 +266,27 @@ def test_fusion_autotune_keeps_the_arena_and_graph(stream):
             Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 9)
     finally:
         Q.qd_batch_free(b)
-        Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 0)
+        for prm in (Q.QD_TUNE_BATCH_FUSE, Q.QD_TUNE_BATCH_SPT_MID, Q.QD_TUNE_BATCH_SPT_WIDE):
+            Q.qd_tune_set(prm, 0)
+
+
+@pytest.mark.parametrize("mid,wide", [(1, 1), (8, 4), (0, 8)])
+def test_slice_class_shapes_keep_results(stream, mid, wide):
+    """Every slices-per-thread setting of the wide slice classes gives the oracle's states."""
+    circs = small_batch(24, 17, seed=85)
+    ga, L = all_layers(circs)
+    b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C128, stream)
+    try:
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT_MID, mid)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT_WIDE, wide)
+        Q.qd_batch_apply_layers(b, ga, L, 8)
+        states = split(Q.qd_batch_download(b, np.complex128), b, circs)
+    finally:
+        Q.qd_batch_free(b)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT_MID, 0)
+        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT_WIDE, 0)
+    for c, psi in zip(circs, states):
+        assert max_abs(psi, O.run_circuit(c)) <= 1e-12
 
 
 def test_full_4096_circuits_at_the_tuned_width(stream):
@@ -285,7 +307,8 @@ def test_full_4096_circuits_at_the_tuned_width(stream):
         arena = Q.qd_batch_download(b)
     finally:
         Q.qd_batch_free(b)
-        Q.qd_tune_set(Q.QD_TUNE_BATCH_FUSE, 0)
+        for prm in (Q.QD_TUNE_BATCH_FUSE, Q.QD_TUNE_BATCH_SPT_MID, Q.QD_TUNE_BATCH_SPT_WIDE):
+            Q.qd_tune_set(prm, 0)
     offs = np.cumsum([0] + [c.D for c in circs])
     p = (arena.real.astype(np.float64) ** 2 + arena.imag.astype(np.float64) ** 2)
     norms = np.add.reduceat(p, offs[:-1])

@@ -152,9 +152,19 @@ def test_tune_parameters():
         Q.qd_tune_set(p, 0)
         assert Q.qd_tune_get(p) == old
     for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 100), (Q.QD_TUNE_DIRECT_SPT, 3), (Q.QD_TUNE_TILE_ELEMS, 1000),
-                 (Q.QD_TUNE_BATCH_GRID, 65), (42, 1)):
+                 (Q.QD_TUNE_BATCH_GRID, 65), (Q.QD_TUNE_BATCH_FUSE, 9), (Q.QD_TUNE_BATCH_SPT_MID, 3),
+                 (Q.QD_TUNE_BATCH_SPT_WIDE, 16), (42, 1)):
         with pytest.raises(Q.QDError):
             Q.qd_tune_set(p, v)
+
+
+def test_batch_slice_class_parameters():
+    """Slices per thread of the wide batched slice classes: 0 is the default rule, else 1, 2, 4, 8."""
+    for p in (Q.QD_TUNE_BATCH_SPT_MID, Q.QD_TUNE_BATCH_SPT_WIDE):
+        assert Q.qd_tune_get(p) == 0
+        for v in (1, 2, 4, 8, 0):
+            Q.qd_tune_set(p, v)
+            assert Q.qd_tune_get(p) == v
 
 
 # ------------------------------------------------------------------------------ fusion planner
@@ -269,18 +279,24 @@ def test_tune_load_and_save(tmp_path):
     p = tmp_path / "tune.json"
     # stride class 4 (>= 256) tiled: qudit 2 (stride 288) is staged in LDS
     p.write_text('[\n{"prec": 0, "bucket": 4, "tiled": 1, "block": 256, "spt": 1, "tile_elems": 2048},\n'
-                 '{"batch_block": 128, "batch_spt": 4}\n]\n')
+                 '{"batch_block": 128, "batch_spt": 4, "batch_grid": 32, "batch_fuse": 6, "batch_spt_mid": 2, '
+                 '"batch_spt_wide": 1}\n]\n')
     Q.qd_tune_load(str(p))
     try:
         assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_TILED
         assert Q.qd_tune_get(Q.QD_TUNE_BATCH_BLOCK) == 128 and Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT) == 4
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_GRID) == 32 and Q.qd_tune_get(Q.QD_TUNE_BATCH_FUSE) == 6
+        assert Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_MID) == 2 and Q.qd_tune_get(Q.QD_TUNE_BATCH_SPT_WIDE) == 1
         out = tmp_path / "saved.json"
         Q.qd_tune_save(str(out))
-        assert '"bucket": 4, "tiled": 1' in out.read_text()
+        text = out.read_text()
+        assert '"bucket": 4, "tiled": 1' in text
+        assert '"batch_fuse": 6, "batch_spt_mid": 2, "batch_spt_wide": 1' in text
     finally:
         # an explicit setting discards the tuned table and restores the defaults
-        Q.qd_tune_set(Q.QD_TUNE_BATCH_BLOCK, 0)
-        Q.qd_tune_set(Q.QD_TUNE_BATCH_SPT, 0)
+        for prm in (Q.QD_TUNE_BATCH_BLOCK, Q.QD_TUNE_BATCH_SPT, Q.QD_TUNE_BATCH_GRID, Q.QD_TUNE_BATCH_FUSE,
+                    Q.QD_TUNE_BATCH_SPT_MID, Q.QD_TUNE_BATCH_SPT_WIDE):
+            Q.qd_tune_set(prm, 0)
     assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_DIRECT
     bad = tmp_path / "bad.json"
     bad.write_text('[{"prec": 0, "bucket": 9, "tiled": 1, "block": 256, "spt": 1, "tile_elems": 2048}]\n')
