@@ -1,12 +1,14 @@
 // Batched circuits: many independent registers of different sizes in one device arena, advanced
-// one gate layer (the paper's Moment, Sec. 3.5) at a time by ONE persistent launch per layer.
+// one gate layer (the paper's Moment, Sec. 3.5) at a time by ONE launch per layer.
 //
-// A layer holds at most one single-target gate (optionally with one control) per circuit. The host
-// turns it into a descriptor per circuit (arena offset, slice map, U) and a prefix sum of work
-// tiles (a tile is `block x spt` consecutive slices of one circuit). Each workgroup walks a
-// contiguous range of the global tile list: one binary search to find its first circuit, then it
-// steps forward, so heterogeneous registers and gates share one launch with divergence only
-// between tiles, never inside a wavefront. Layers can be recorded into a hipGraph and replayed.
+// A layer holds at most one single-target gate (optionally with one control) per circuit; a
+// circuit's consecutive gates may also be composed on the host into one operation on up to four
+// qudits (qd_batch_apply_layers). The host turns each circuit's operation into a descriptor
+// (arena offset, slice map, slice offsets, U) and a prefix sum of work tiles (a tile is
+// `block x spt` consecutive slices of one circuit), plus a table giving each tile's circuit. A
+// workgroup copies its tile's descriptor and U to LDS and walks the tile, so heterogeneous
+// registers and gates share one launch with divergence only between tiles, never inside a
+// wavefront. Launches can be recorded into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +28,7 @@ constexpr int kBatchMaxFuse = 8;    // gates composed into one operation
 struct BatchDesc {
   int64_t off;                      // arena offset of the circuit's state (amplitudes)
   int64_t base;                     // control offset inside the state
-  int64_t st;                       // target stride of a one-target operation, 0 for a fused one
+  int64_t st;                       // target stride of a one-gate operation, 0 for a composed one
   uint32_t nwork;                   // active slices
   uint32_t tile0;                   // first global tile of this circuit
   int32_t dt;                       // slice size d_T, 0 = nothing for this circuit in this launch
@@ -37,7 +39,7 @@ struct BatchDesc {
   uint32_t pad2[kBatchGroups & 1 ? 1 : 2];
   Magic32 gmag[kBatchGroups];
   int64_t gstride[kBatchGroups];
-  int64_t yoff[kBatchMaxSlice];     // offset of local index y inside a slice (fused operations)
+  int64_t yoff[kBatchMaxSlice];     // offset of local index y inside a slice
 };
 
 template <typename R>
@@ -292,7 +294,8 @@ struct BatchOp {
 
 static bool slice_supported(int dT) { return (dT >= 2 && dT <= 9) || dT == 12 || dT == 16; }
 
-// Host: descriptors and U pool of one launch; returns the total tile count.
+// Host: descriptors and U pool of one launch; *ntiles the total tile count, *maxdt the largest slice
+// of a composed operation (0 when the launch holds one-gate operations only).
 template <typename R>
 static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector<BatchDesc>* desc,
                        std::vector<R>* pool, uint32_t* ntiles, int* maxdt) {
