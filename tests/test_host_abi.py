@@ -304,3 +304,14 @@ def test_tune_load_and_save(tmp_path):
         Q.qd_tune_load(str(bad))
     with pytest.raises(Q.QDError):
         Q.qd_tune_load(str(tmp_path / "missing.json"))
+
+
+def test_batch_create_rejects_before_device_work():
+    """Batch creation validates every register before it allocates: bad precision, a bad radix and a
+    register of D >= 2^32 fail with no device call (this runs without a GPU)."""
+    cases = (([[2, 3]], 7, Q.QD_EINVAL), ([[2, 257]], Q.QD_C64, Q.QD_EDIM),
+             ([[2, 3], [2] * 32], Q.QD_C64, Q.QD_EOVERFLOW))
+    for dims_list, prec, code in cases:
+        with pytest.raises(Q.QDError) as e:
+            Q.qd_batch_create(dims_list, prec, 0)
+        assert e.value.code == code, (dims_list, prec)
