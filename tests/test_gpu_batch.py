@@ -322,3 +322,29 @@ def test_full_4096_circuits_at_the_tuned_width(stream):
             assert fidelity_loss(O.run_circuit(c), psi) <= 1e-6, i
         plain = run_gpu(c, Q.QD_C64, stream)
         assert max_abs(plain, psi) <= 4 * 100 * 16 * U24, i
+
+
+def test_empty_layers_are_no_ops(stream):
+    """No layers, and layers whose every slot is empty, leave the arena as it is at any width."""
+    circs = small_batch(8, 6, seed=86)
+    ga, L = all_layers(circs)
+    nc = len(circs)
+    b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C128, stream)
+    try:
+        Q.qd_batch_apply_layers(b, ga, 3, 1)
+        before = Q.qd_batch_download(b, np.complex128)
+        Q.qd_batch_apply_layers(b, ga, 0, 4)
+        empty = Q.GateArray([None] * (2 * nc), lambda j: circs[j % nc].dims)
+        for w in (1, 2, 8):
+            Q.qd_batch_apply_layers(b, empty, 2, w)
+        assert np.array_equal(Q.qd_batch_download(b, np.complex128), before)
+        # an empty layer between real ones changes nothing either
+        mixed = Q.GateArray([circs[i].gates[0] for i in range(nc)] + [None] * nc + [circs[i].gates[1] for i in range(nc)],
+                            lambda j: circs[j % nc].dims)
+        Q.qd_batch_reset(b)
+        Q.qd_batch_apply_layers(b, mixed, 3, 8)
+        got = split(Q.qd_batch_download(b, np.complex128), b, circs)
+    finally:
+        Q.qd_batch_free(b)
+    for c, psi in zip(circs, got):
+        assert max_abs(psi, O.run_circuit(C.Circuit(c.dims, c.gates[:2]))) <= 1e-12
