@@ -60,7 +60,7 @@ enum { QD_MODE_FP64_PLAIN = 0, QD_MODE_FP32_MFMA = 1, QD_MODE_BF16X3_MFMA = 2 };
 enum { QD_FLAG_SKIP_UNITARY_CHECK = 1 };
 enum { QD_GATE_X = 0, QD_GATE_Z = 1, QD_GATE_F = 2, QD_GATE_I = 3 };   /* named gates, Sec. 2.1 */
 enum { QD_CLASS_DENSE = 0, QD_CLASS_MONOMIAL = 1, QD_CLASS_DIAGONAL = 2 };
-enum { QD_ROUTE_DIRECT = 0, QD_ROUTE_TILED = 1, QD_ROUTE_DIAG = 2, QD_ROUTE_GENERIC = 3 };
+enum { QD_ROUTE_DIRECT = 0, QD_ROUTE_TILED = 1, QD_ROUTE_DIAG = 2, QD_ROUTE_GENERIC = 3, QD_ROUTE_GEMM = 4 };
 
 #define QD_MAX_QUDITS 64    /* n <= 64 */
 #define QD_MAX_RADIX 256    /* 2 <= dims[i] <= 256 */
@@ -119,6 +119,8 @@ int qd_gate_class(const double* U, int32_t dT);
  *   QD_ROUTE_DIRECT  one slice per thread (every target stride >= the run threshold);
  *   QD_ROUTE_TILED   slices staged in LDS (a target with a small stride);
  *   QD_ROUTE_DIAG    elementwise phases (diagonal U);
+ *   QD_ROUTE_GEMM    dense 10 <= d_T <= 64 (and other monomials in that range): per tile of
+ *                    slices a small complex GEMM, U and the tile in LDS;
  *   QD_ROUTE_GENERIC any d_T up to 1024 or D >= 2^32 (U in device memory).
  * Validation as in qd_apply_gate. */
 int qd_gate_route(const int32_t* dims, int32_t n, int32_t prec, const int32_t* targets, int32_t k,

@@ -31,7 +31,7 @@ __all__ = [
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
     "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "QD_TUNE_BATCH_SPT_MID", "QD_TUNE_BATCH_SPT_WIDE",
     "qd_batch_apply_layers", "qd_batch_autotune_layers",
-    "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "qd_gate_route",
+    "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "QD_ROUTE_GEMM", "qd_gate_route",
     "qd_version", "qd_last_error", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
@@ -61,7 +61,7 @@ QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
 QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2
 QD_CHANNEL_DEPOLARIZING, QD_CHANNEL_DEPHASING, QD_CHANNEL_AMPLITUDE_DAMPING = 0, 1, 2
 QD_OP_GATE, QD_OP_CHANNEL = 0, 1
-QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC = 0, 1, 2, 3
+QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC, QD_ROUTE_GEMM = 0, 1, 2, 3, 4
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
  QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID,
  QD_TUNE_BATCH_FUSE, QD_TUNE_BATCH_SPT_MID, QD_TUNE_BATCH_SPT_WIDE) = range(13)

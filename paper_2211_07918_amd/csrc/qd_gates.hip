@@ -332,6 +332,150 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
   }
 }
 
+// ------------------------------------------------------------------------------------------ gemm
+// Dense gates with kGemmMin <= d_T <= kGemmMax on registers below 2^32 amplitudes: per tile of ns
+// slices, Y = U X as a small complex GEMM. U (zero-padded to dP = d_T rounded up to a multiple of 4,
+// rows kGemmPad elements apart so the rows a wavefront reads fall in different banks) and the
+// tile's X (dP rows x ns slices) sit in LDS; each thread accumulates a 4 x 4 block of outputs in
+// registers; the results go back through LDS, so loads and stores both run over consecutive
+// slices. Workgroups are persistent and stage U once.
+constexpr int kGemmMin = 10;
+constexpr int kGemmMax = 64;
+constexpr int kGemmOut = 4096;        // outputs per tile (dP x ns), 16 per thread
+// The tile moves between HBM and LDS element by element in one of two orders: slices fastest (the
+// free digits hold the smallest stride), or target combinations fastest in ascending offset (a
+// target holds the smallest stride), so that consecutive lanes touch neighbouring amplitudes.
+struct GemmHead {
+  SliceMap sm;                        // slices: the non-target digits (controls fixed)
+  Magic32 nsm;                        // division by ns
+  Magic32 dpm;                        // division by dP
+  int32_t dT, dP, ns, yfast;
+  // followed by int64_t toff[dT], int32_t yord[dP] (target combinations by ascending offset, then
+  // the padding rows) and 2 dP^2 values of R (U zero-padded, row-major)
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_gemm(R* psi_raw, const unsigned char* desc) {
+  using C = typename CxT<R>::T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const GemmHead& h = *reinterpret_cast<const GemmHead*>(desc);
+  // the head is read into locals and LDS before the first store: read later from global memory it
+  // would be fetched again by vector loads (the stores could alias it)
+  __shared__ SliceMap smap;
+  static_assert(sizeof(SliceMap) % 4 == 0, "slice map copied in 4-byte words");
+  for (uint32_t i = threadIdx.x; i < sizeof(SliceMap) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&smap)[i] = reinterpret_cast<const uint32_t*>(&h.sm)[i];
+  const Magic32 nsm = h.nsm, dpm = h.dpm;
+  const uint32_t dT = uint32_t(h.dT), dP = uint32_t(h.dP), ns = uint32_t(h.ns), ldu = dP + 1;
+  const uint32_t count = h.sm.count;
+  C* __restrict__ psi = reinterpret_cast<C*>(psi_raw);
+  C* xs = reinterpret_cast<C*>(lds_raw);                        // dP x ns, element (y, j) at y ns + j
+  C* us = xs + dP * ns;                                         // dP x dP, row stride ldu
+  int64_t* sb = reinterpret_cast<int64_t*>(us + dP * ldu);     // ns slice bases
+  int64_t* to = sb + ns;                                        // dT target offsets
+  int32_t* yo = reinterpret_cast<int32_t*>(to + dT);            // dP rows in memory order
+  const int64_t* tg = reinterpret_cast<const int64_t*>(desc + sizeof(GemmHead));
+  const int32_t* yg = reinterpret_cast<const int32_t*>(desc + sizeof(GemmHead) + sizeof(int64_t) * dT);
+  const R* ug = reinterpret_cast<const R*>(desc + sizeof(GemmHead) + sizeof(int64_t) * dT + sizeof(int32_t) * dP);
+  const bool yfast = h.yfast != 0;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < dP * dP; i += blockDim.x) {
+    const uint32_t r = i / dP, c = i - r * dP;
+    C v;
+    v.x = ug[2 * i];
+    v.y = ug[2 * i + 1];
+    us[r * ldu + c] = v;
+  }
+  for (uint32_t i = tid; i < dT; i += blockDim.x) to[i] = tg[i];
+  for (uint32_t i = tid; i < dP; i += blockDim.x) yo[i] = yg[i];
+  const uint32_t rbn = dP / 4, nblk = rbn * (ns / 4);
+  const uint32_t rb = tid % rbn, kb = tid / rbn;                // this thread's 4 x 4 output block
+  const uint32_t ntiles = (count + ns - 1) / ns;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t s0 = tile * ns;
+    __syncthreads();   // U staged; the previous tile is stored
+    for (uint32_t j = tid; j < ns; j += blockDim.x) sb[j] = s0 + j < count ? sm_offset(smap, s0 + j) : int64_t(-1);
+    __syncthreads();
+    // every load of the tile in flight before the first LDS write (at most kGemmOut / 256 each)
+    {
+      constexpr int EPT = kGemmOut / 256;
+      const uint32_t tot = dP * ns;
+      C v[EPT];
+      uint32_t at[EPT];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const uint32_t e = tid + uint32_t(k) * 256u;
+        v[k].x = R(0);
+        v[k].y = R(0);
+        at[k] = 0xFFFFFFFFu;
+        if (e < tot) {
+          uint32_t y, j;
+          if (yfast) {
+            j = magic_div(e, dpm);
+            y = uint32_t(yo[e - j * dP]);
+          } else {
+            y = magic_div(e, nsm);
+            j = e - y * ns;
+          }
+          at[k] = y * ns + j;
+          if (y < dT && sb[j] >= 0) v[k] = ld_stream(psi + (sb[j] + to[y]));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        if (at[k] != 0xFFFFFFFFu) xs[at[k]] = v[k];
+    }
+    __syncthreads();
+    C acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc[i][k].x = R(0);
+        acc[i][k].y = R(0);
+      }
+    if (tid < nblk) {
+      const C* ur = us + 4 * rb * ldu;
+      const C* xc = xs + 4 * kb;
+      for (uint32_t c = 0; c < dP; ++c) {
+        C u[4], x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = ur[i * ldu + c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = xc[c * ns + k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            acc[i][k].x = fma(u[i].x, x[k].x, acc[i][k].x);
+            acc[i][k].x = fma(-u[i].y, x[k].y, acc[i][k].x);
+            acc[i][k].y = fma(u[i].x, x[k].y, acc[i][k].y);
+            acc[i][k].y = fma(u[i].y, x[k].x, acc[i][k].y);
+          }
+      }
+    }
+    __syncthreads();   // every product has read X
+    if (tid < nblk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xs[(4 * rb + i) * ns + 4 * kb + k] = acc[i][k];
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < dP * ns; e += blockDim.x) {
+      uint32_t y, j;
+      if (yfast) {
+        j = magic_div(e, dpm);
+        y = uint32_t(yo[e - j * dP]);
+      } else {
+        y = magic_div(e, nsm);
+        j = e - y * ns;
+      }
+      if (y < dT && sb[j] >= 0) st_stream(psi + (sb[j] + to[y]), xs[y * ns + j]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------ launch helpers
 static inline unsigned grid_for(uint64_t items, uint64_t per_block) {
   const uint64_t g = (items + per_block - 1) / per_block;
@@ -422,7 +566,7 @@ int route_gate(const Register& r, int prec, const GatePlan& p) {
   const bool mono = p.cls == QD_CLASS_MONOMIAL &&
                     (p.dT <= 9 || p.dT == 12 || p.dT == 16);
   const bool dense = p.cls != QD_CLASS_DIAGONAL && p.dT <= kMaxInlineDense;
-  if (!mono && !dense) return QD_ROUTE_GENERIC;
+  if (!mono && !dense) return p.dT >= kGemmMin && p.dT <= kGemmMax ? QD_ROUTE_GEMM : QD_ROUTE_GENERIC;
   TileGeom g;
   return tile_geometry(r, p, prec, &g) ? QD_ROUTE_TILED : QD_ROUTE_DIRECT;
 }
@@ -594,9 +738,64 @@ static int launch_generic(qd_state* s, const GatePlan& p) {
 }
 
 template <typename R>
+static int launch_gemm(qd_state* s, const GatePlan& p) {
+  const Register& r = s->reg;
+  int role[QD_MAX_QUDITS] = {};
+  for (int j = 0; j < p.k; ++j) role[p.targets[j]] = 1;
+  for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
+  int64_t base = 0;
+  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  const int dT = p.dT, dP = (dT + 3) / 4 * 4, ns = (kGemmOut / dP) / 4 * 4;
+  const size_t bytes = sizeof(GemmHead) + sizeof(int64_t) * size_t(dT) + sizeof(int32_t) * size_t(dP) +
+                       sizeof(R) * 2 * size_t(dP) * dP;
+  std::vector<unsigned char> buf(bytes, 0);
+  auto* h = reinterpret_cast<GemmHead*>(buf.data());
+  const std::vector<Group> groups = make_groups(r, role, nullptr, 0, r.n);
+  if (fill_slicemap(groups, base, &h->sm) != QD_OK) return launch_generic<R>(s, p);
+  h->nsm = make_magic32(uint32_t(ns));
+  h->dpm = make_magic32(uint32_t(dP));
+  h->dT = dT;
+  h->dP = dP;
+  h->ns = ns;
+  int64_t* toff = reinterpret_cast<int64_t*>(buf.data() + sizeof(GemmHead));
+  target_offsets(r, p, toff);
+  int32_t* yord = reinterpret_cast<int32_t*>(buf.data() + sizeof(GemmHead) + sizeof(int64_t) * size_t(dT));
+  for (int y = 0; y < dP; ++y) yord[y] = y;
+  std::sort(yord, yord + dT, [&](int32_t a, int32_t b) { return toff[a] < toff[b]; });
+  int64_t tmin = INT64_MAX;
+  for (int j = 0; j < p.k; ++j) tmin = std::min<int64_t>(tmin, r.strides[p.targets[j]]);
+  h->yfast = groups.empty() || tmin < groups[0].stride ? 1 : 0;   // groups[0]: the lowest free run
+  R* U = reinterpret_cast<R*>(buf.data() + sizeof(GemmHead) + sizeof(int64_t) * size_t(dT) + sizeof(int32_t) * size_t(dP));
+  for (int a = 0; a < dT; ++a)
+    for (int c = 0; c < dT; ++c) {
+      U[2 * (size_t(a) * dP + c)] = R(p.U[2 * (size_t(a) * dT + c)]);
+      U[2 * (size_t(a) * dP + c) + 1] = R(p.U[2 * (size_t(a) * dT + c) + 1]);
+    }
+  if (h->sm.count == 0) return QD_OK;
+  void* dev = nullptr;
+  int rc = ring_push(s, buf.data(), bytes, &dev);
+  if (rc) return rc;
+  using C = typename CxT<R>::T;
+  const size_t lds = size_t(dP) * ns * sizeof(C) + size_t(dP) * (dP + 1) * sizeof(C) + sizeof(int64_t) * size_t(ns + dT) +
+                     sizeof(int32_t) * size_t(dP);
+  auto k = k_dense_gemm<R>;
+  QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  int dev_id = 0, cus = 256, per_cu = 0;
+  (void)hipGetDevice(&dev_id);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  const uint64_t ntiles = (uint64_t(h->sm.count) + ns - 1) / ns;
+  const unsigned grid = unsigned(std::min<uint64_t>(ntiles, uint64_t(cus) * per_cu));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s->stream, reinterpret_cast<R*>(s->data),
+                     static_cast<const unsigned char*>(dev));
+  return check_launch("k_dense_gemm");
+}
+
+template <typename R>
 static int launch_gate_t(qd_state* s, const GatePlan& p) {
   const int route = route_gate(s->reg, s->prec, p);
   if (route == QD_ROUTE_GENERIC) return launch_generic<R>(s, p);
+  if (route == QD_ROUTE_GEMM) return launch_gemm<R>(s, p);
   if (route == QD_ROUTE_DIAG) return launch_diag<R>(s, p);
   if (p.cls == QD_CLASS_MONOMIAL) {
     switch (p.dT) {

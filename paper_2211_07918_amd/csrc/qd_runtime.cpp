@@ -265,7 +265,8 @@ void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, c
   }
   GatePlan q;
   make_plan(r, t2.data(), int32_t(t2.size()), c2.data(), v2.data(), int32_t(c2.size()), G.data(), &q);
-  if (route_gate(r, prec, q) != QD_ROUTE_GENERIC) *p = std::move(q);
+  const int route = route_gate(r, prec, q);   // fold only into the slice-per-thread, tiled or diagonal kernels
+  if (route != QD_ROUTE_GENERIC && route != QD_ROUTE_GEMM) *p = std::move(q);
 }
 
 // ------------------------------------------------------------------------------------------ groups

@@ -126,13 +126,16 @@ def test_every_route_is_exercised(stream):
         ([0], (), (), C.haar_unitary(3, rng), Q.QD_ROUTE_DIRECT),
         ([9], (), (), C.haar_unitary(2, rng), Q.QD_ROUTE_TILED),
         ([6, 9], (0,), (2,), C.haar_unitary(6, rng), Q.QD_ROUTE_TILED),
-        ([2, 0], (9,), (1,), C.haar_unitary(12, rng), Q.QD_ROUTE_GENERIC),
+        ([2, 0], (9,), (1,), C.haar_unitary(12, rng), Q.QD_ROUTE_GEMM),
         ([9], (3,), (1,), O.z_gate(2), Q.QD_ROUTE_DIAG),
         ([2, 3], (), (), np.diag(np.exp(2j * np.pi * rng.random(12))), Q.QD_ROUTE_DIAG),
         ([1], (0,), (2,), O.x_gate(2, 1), Q.QD_ROUTE_DIRECT),
         ([2, 0], (), (), np.eye(12)[rng.permutation(12)] * np.exp(1j * rng.random(12)), Q.QD_ROUTE_DIRECT),
         ([8, 9], (), (), np.eye(4)[rng.permutation(4)], Q.QD_ROUTE_TILED),
-        ([0, 1, 2], (9,), (0,), C.haar_unitary(24, rng), Q.QD_ROUTE_GENERIC),
+        ([0, 1, 2], (9,), (0,), C.haar_unitary(24, rng), Q.QD_ROUTE_GEMM),
+        ([9, 3, 0], (), (), C.haar_unitary(18, rng), Q.QD_ROUTE_GEMM),
+        ([2, 3, 6], (0,), (1,), C.haar_unitary(36, rng), Q.QD_ROUTE_GEMM),
+        ([0, 1, 2, 3], (), (), C.haar_unitary(72, rng), Q.QD_ROUTE_GENERIC),
     ]
     for prec in (Q.QD_C128, Q.QD_C64):
         for t, c, v, U, route in cases:
@@ -368,3 +371,32 @@ def test_config1_full_size_diagonal_closed_form(stream):
         want.append(psi0[x] * complex(math.cos(2 * math.pi * ang), math.sin(2 * math.pi * ang)))
     assert max_abs(psi[idx], np.array(want)) <= 1e-12
     assert np.count_nonzero(psi) == len(idx)
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_gemm_route_sizes(stream, prec):
+    """Dense gates of 10 <= d_T <= 64 run as a small GEMM per tile of slices: padded and unpadded d_T
+    (10, 15, 16, 18, 20, 24, 28, 32, 64), with and without a control, on a register whose slice
+    count leaves a ragged last tile; each result against the oracle."""
+    dims = (2, 5, 3, 4, 7, 2, 3, 4, 2)
+    rng = C.seeded_rng(91)
+    D = O.register_size(dims)
+    psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    cases = [((0, 1), (), ()), ((2, 1), (0,), (1,)), ((3, 1), (), ()), ((4, 3), (8,), (0,)),
+             ((3, 7, 0), (), ()), ((8, 3, 6), (2,), (2,)), ((3, 7, 5, 0), (), ()), ((3, 7), (1,), (4,)),
+             ((2, 6, 8), (), ())]
+    for t, c, v in cases:
+        dT = int(np.prod([dims[q] for q in t]))
+        U = C.haar_unitary(dT, rng)
+        assert Q.qd_gate_route(dims, prec, t, c, v, U) == (Q.QD_ROUTE_GEMM if 10 <= dT <= 64 else Q.QD_ROUTE_DIRECT), (t, dT)
+        s = Q.qd_state_init(dims, prec, stream)
+        try:
+            Q.qd_state_upload(s, psi0)
+            Q.qd_apply_gate(s, t, c, v, U)
+            out = Q.qd_state_download(s)
+        finally:
+            Q.qd_state_free(s)
+        ref = O.apply_gate(psi0, dims, t, c, v, U)
+        tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, dT)
+        assert max_abs(out, ref) <= tol, (t, c, dT, prec)
