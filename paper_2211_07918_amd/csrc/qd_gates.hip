@@ -301,19 +301,27 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* xs = reinterpret_cast<C*>(lds_raw);
   const GenericHead& h = *reinterpret_cast<const GenericHead*>(desc);
+  // the slice map is read into LDS before the first store (read later from global memory it would
+  // be fetched again by vector loads, the stores could alias it)
+  __shared__ SliceMap64 smap;
+  static_assert(sizeof(SliceMap64) % 4 == 0, "slice map copied in 4-byte words");
+  for (uint32_t i = threadIdx.x; i < sizeof(SliceMap64) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&smap)[i] = reinterpret_cast<const uint32_t*>(&h.sm)[i];
   const int64_t* toff = reinterpret_cast<const int64_t*>(desc + sizeof(GenericHead));
   const R* U = reinterpret_cast<const R*>(desc + sizeof(GenericHead) + sizeof(int64_t) * h.dT);
   C* psi = reinterpret_cast<C*>(psi_raw);
   const uint32_t dT = uint32_t(h.dT), nsw = uint32_t(h.nsw), tot = dT * nsw;
-  for (uint64_t s0 = uint64_t(blockIdx.x) * nsw; s0 < h.sm.count; s0 += uint64_t(gridDim.x) * nsw) {
+  const uint64_t count = h.sm.count;
+  __syncthreads();
+  for (uint64_t s0 = uint64_t(blockIdx.x) * nsw; s0 < count; s0 += uint64_t(gridDim.x) * nsw) {
     for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
       const uint32_t j = e / dT, y = e - j * dT;
-      if (s0 + j < h.sm.count) xs[e] = ld_stream(psi + (sm64_offset(h.sm, s0 + j) + toff[y]));
+      if (s0 + j < count) xs[e] = ld_stream(psi + (sm64_offset(smap, s0 + j) + toff[y]));
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < tot; e += blockDim.x) {
       const uint32_t j = e / dT, row = e - j * dT;
-      if (s0 + j >= h.sm.count) continue;
+      if (s0 + j >= count) continue;
       R re = R(0), im = R(0);
       const R* u = U + 2 * size_t(row) * dT;
       const C* x = xs + j * dT;
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(256) void k_dense_generic(R* psi_raw, const unsigne
       C y;
       y.x = re;
       y.y = im;
-      st_stream(psi + (sm64_offset(h.sm, s0 + j) + toff[row]), y);
+      st_stream(psi + (sm64_offset(smap, s0 + j) + toff[row]), y);
     }
     __syncthreads();
   }
