@@ -486,15 +486,15 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
     circ, ops = _noisy_ops(C, dims, 60, 1008)
     kraus = {d: Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, d, 1e-3) for d in set(dims)}
     lib_ops = [o if o[0] == "gate" else ("chan", (o[1],), kraus[dims[o[1]]]) for o in ops]
-    # passes, as qd_density_apply_ops forms them: a run of consecutive operations on the same single
-    # target with no controls and d <= 3 is one composed pass over all D^2 elements; any other
+    # passes, as qd_density_apply_ops forms them: a run of consecutive operations on the same
+    # targets with no controls and d_T <= 4 is one composed pass over all D^2 elements; any other
     # channel is one pass; any other gate is one pass when its embedding on targets and controls
-    # has d_G <= 3 (dense U) or <= 4 (monomial or diagonal U), else two, each touching the
-    # D^2 / d_c elements whose control digits match
+    # has d_G <= 4 (d_G <= 3 for a dense U with controls), else two, each touching the D^2 / d_c
+    # elements whose control digits match
     def fusable(o):
         t = o[1].targets if o[0] == "gate" else (o[1],)
         ctl = o[1].controls if o[0] == "gate" else ()
-        return (not ctl and len(t) == 1 and dims[t[0]] <= 3), tuple(t)
+        return (not ctl and int(np.prod([dims[q] for q in t])) <= 4), tuple(t)
 
     passes, active, i = 0, 0, 0
     while i < len(ops):
@@ -510,7 +510,8 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
             g = ops[i][1]
             dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
             dG = int(np.prod([dims[q] for q in g.targets])) * dc
-            fused = dG <= (4 if Q.qd_gate_class(Q.gate_unitary(g, dims)) != Q.QD_CLASS_DENSE else 3)
+            dense = Q.qd_gate_class(Q.gate_unitary(g, dims)) == Q.QD_CLASS_DENSE
+            fused = dG <= (3 if dense and g.controls else 4)
             passes += 1 if fused else 2
             active += D * D if fused else 2 * (D * D // dc)
         i = j

@@ -7,9 +7,9 @@
 // at flat index x * D + y (row-major). With this layout
 //   * a gate G maps rho -> G rho G^dagger, i.e. G on the row qudits and conj(G) on the column
 //     qudits. With G embedded on its targets and controls (dimension d_G = d_T x d_C), a gate with
-//     d_G <= kFuseGate (dense U) or d_G <= kFuseMono (monomial or diagonal U) is one pass of
-//     G (x) conj(G) over (T, C, T + n, C + n); other gates take two passes (U on T with its
-//     controls, conj(U) on T + n with the shifted controls);
+//     d_G <= kFuseGate (dense U; kFuseGateFree without controls) or d_G <= kFuseMono (monomial or
+//     diagonal U) is one pass of G (x) conj(G) over (T, C, T + n, C + n); other gates take two
+//     passes (U on T with its controls, conj(U) on T + n with the shifted controls);
 //   * a channel with Kraus operators K_1..K_r maps rho -> sum_k K_k rho K_k^dagger, one pass of the
 //     superoperator S = sum_k K_k (x) conj(K_k) over (T, T + n).
 // Both run through the library's gate kernels (HBM-bound passes over the D^2 elements). The
@@ -29,12 +29,15 @@ namespace dm {
 
 constexpr int kBlock = 256;
 // d_G (targets x controls) up to which a gate is one pass of G (x) conj(G): the superoperator must
-// stay on the fast gate kernels (dense up to 9 x 9, monomial up to 16 x 16; larger ones take the
-// generic kernel, which measured slower than two passes)
+// stay on kernels that beat two passes. Dense superoperators up to 9 x 9 run on the slice kernels;
+// a dense 16 x 16 one takes the GEMM route (0.82-0.86 ms on 1.07e8 elements), which beats two full
+// passes (2 x 0.57 ms) but not the two passes of a controlled gate, which touch only the elements
+// whose control digits match (2 x 0.36 ms with a qubit control); monomial ones up to 16 x 16.
 constexpr int kFuseGate = 3;          // dense U
+constexpr int kFuseGateFree = 4;      // dense U without controls
 constexpr int kFuseMono = 4;          // monomial or diagonal U
 constexpr int kMaxChannelDim = 32;    // d_T of a channel (its superoperator is d_T^2 x d_T^2 <= 1024)
-constexpr int kFuseGroup = 3;         // d_T up to which a run of operations on the same targets is one pass
+constexpr int kFuseGroup = 4;         // d_T up to which a run of operations on the same targets is one pass
 constexpr int kRedGrid = 1024;
 
 template <typename R> struct Cx;
@@ -231,7 +234,7 @@ int qd_density_apply_gate(qd_state* rho, const int32_t* targets, int32_t k, cons
   const int dG = dT * dC;                 // the gate embedded on (targets, controls)
   const uint32_t skip = flags | QD_FLAG_SKIP_UNITARY_CHECK;
   const bool mono = classify(U, dT) != QD_CLASS_DENSE;
-  if ((mono && dG <= kFuseMono) || (!mono && dG <= kFuseGate)) {
+  if ((mono && dG <= kFuseMono) || (!mono && dG <= (m == 0 ? kFuseGateFree : kFuseGate))) {
     // one pass of G (x) conj(G) over (T, C, T + n, C + n), G[(t, c), (t', c')] = delta(c, c') times
     // U[t][t'] when the control digits c hold the control values, else delta(t, t')
     std::vector<double> G(2 * size_t(dG) * dG, 0.0);
