@@ -575,14 +575,15 @@ def bench_density_cpu(C, seconds):
             "sample": f"{done} operations of the same recipe on 3 qubits + 2 qutrits (D = {D}), NumPy, 1 thread, {dt:.1f} s"}
 
 
-_BATCH_SLICES = set(range(2, 10)) | {12, 16}
+_BATCH_SLICES = set(range(2, 10)) | {12, 16, 18, 24, 27, 32}
 
 
 def batch_schedule(circs, W):
     """Launches and algorithmic bytes (complex64, read + write of every amplitude a pass touches) of
     qd_batch_apply_layers at fusion width W, by the library's block rule: a circuit's next gates
     join a block while it has at most W of them and their qudits number at most 4 with a slice
-    size in {2..9, 12, 16}; a one-gate block touches D / d_c amplitudes, a composed one all D."""
+    size in {2..9, 12, 16, 18, 24, 27, 32}; a one-gate block touches D / d_c amplitudes, a composed
+    one all D."""
     import numpy as np
     launches, nbytes = 0, 0
     for c in circs:

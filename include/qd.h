@@ -536,7 +536,8 @@ int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
 /* nlayers layers (gates[l * nc + c] acts on circuit c in layer l; k == 0 = no gate) with the
  * gates of each circuit fused into blocks: a block takes the circuit's next gates in order while
  * it has at most `width` of them (1..8; 0 = the tuned QD_TUNE_BATCH_FUSE) and the union of their
- * qudits (targets and controls) has at most 4 qudits of total dimension in {2..9, 12, 16}. A
+ * qudits (targets and controls) has at most 4 qudits of total dimension in {2..9, 12, 16, 18, 24,
+ * 27, 32}. A
  * block of several gates is composed on the host in FP64 into one operation on that union (each
  * U embedded, the identity where its control misses) and applied in one pass over the state.
  * Launch i applies every circuit's i-th block, so the launch count is the most blocks of any
@@ -578,7 +579,7 @@ void qd_batch_free(qd_batch* b);
  * in LDS (QD_TUNE_RUN_MIN, 1..1024 amplitudes) and the workgroups per compute unit of the batched
  * layer kernel (QD_TUNE_BATCH_GRID: 1..63 persistent workgroups walk the tile list; 64 launches one
  * workgroup per tile), the most gates qd_batch_apply_layers composes into one operation
- * (QD_TUNE_BATCH_FUSE, 1..8) and the slices per thread of batched slices of 5..9 and of 12 or 16
+ * (QD_TUNE_BATCH_FUSE, 1..8) and the slices per thread of batched slices of 5..9 and of 12..32
  * amplitudes (QD_TUNE_BATCH_SPT_MID, QD_TUNE_BATCH_SPT_WIDE: 1, 2, 4 or 8; 0 keeps the rule of two
  * batches of 16 / d_T slices, at most QD_TUNE_BATCH_SPT). 0 restores the default. Process-wide,
  * host only; QD_EINVAL for an unknown parameter or a value outside its range. */

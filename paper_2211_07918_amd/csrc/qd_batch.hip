@@ -21,7 +21,7 @@ namespace qd {
 
 constexpr int kBatchMaxDim = 8;     // target dimension of a gate given to a layer
 constexpr int kBatchMaxTargets = 4; // targets of a fused operation (its union of qudits)
-constexpr int kBatchMaxSlice = 16;  // amplitudes per slice (d_T) of an operation
+constexpr int kBatchMaxSlice = 32;  // amplitudes per slice (d_T) of an operation
 constexpr int kBatchGroups = kBatchMaxTargets + 1;
 constexpr int kBatchMaxFuse = 8;    // gates composed into one operation
 
@@ -141,15 +141,17 @@ __device__ __forceinline__ void batch_tile(const BatchArgs<R>& a, const BatchDes
 }
 
 // MAXDT = 0: a launch of one-gate operations only, addressed y times the target's stride; otherwise
-// every operation of the launch (composed ones with slices of up to 16 amplitudes, and one-gate ones)
-// is addressed through its offset table, so the variant holds one set of cases
+// every operation of the launch (composed ones with slices of up to MAXDT = 16 or 32 amplitudes, and
+// one-gate ones) is addressed through its offset table, so the variant holds one set of cases; the
+// 32 variant (more registers) runs only launches that hold a slice above 16
+template <int MAXDT> constexpr int batch_u_side() { return MAXDT > 16 ? kBatchMaxSlice : 16; }
 template <typename R, int MAXDT>
 __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
   const uint32_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = min(a.ntiles, t0 + per);
   __shared__ BatchDesc d;
-  __shared__ R sU[2 * kBatchMaxSlice * kBatchMaxSlice];
+  __shared__ R sU[2 * batch_u_side<MAXDT>() * batch_u_side<MAXDT>()];
   static_assert(sizeof(BatchDesc) % 8 == 0, "descriptor copied in 8-byte words");
   for (uint32_t t = t0; t < t1; ++t) {
     const BatchDesc* gd = a.desc + a.tmap[t];
@@ -188,6 +190,10 @@ __global__ __launch_bounds__(256) void k_batch_layer(BatchArgs<R> a) {
         case 9: batch_tile<R, 9, true>(a, d, sU, j0, j1); break;
         case 12: batch_tile<R, 12, true>(a, d, sU, j0, j1); break;
         case 16: batch_tile<R, 16, true>(a, d, sU, j0, j1); break;
+        case 18: if constexpr (MAXDT >= 18) batch_tile<R, 18, true>(a, d, sU, j0, j1); break;
+        case 24: if constexpr (MAXDT >= 24) batch_tile<R, 24, true>(a, d, sU, j0, j1); break;
+        case 27: if constexpr (MAXDT >= 27) batch_tile<R, 27, true>(a, d, sU, j0, j1); break;
+        case 32: if constexpr (MAXDT >= 32) batch_tile<R, 32, true>(a, d, sU, j0, j1); break;
         default: break;
       }
     }
@@ -243,7 +249,8 @@ namespace qd {
 
 template <typename R>
 static void* batch_kernel_ptr(int maxdt) {
-  return maxdt == 0 ? reinterpret_cast<void*>(k_batch_layer<R, 0>) : reinterpret_cast<void*>(k_batch_layer<R, 16>);
+  if (maxdt == 0) return reinterpret_cast<void*>(k_batch_layer<R, 0>);
+  return maxdt <= 16 ? reinterpret_cast<void*>(k_batch_layer<R, 16>) : reinterpret_cast<void*>(k_batch_layer<R, 32>);
 }
 
 static void free_graph(qd_batch* b) {
@@ -292,7 +299,9 @@ struct BatchOp {
   std::vector<double> U;
 };
 
-static bool slice_supported(int dT) { return (dT >= 2 && dT <= 9) || dT == 12 || dT == 16; }
+static bool slice_supported(int dT) {
+  return (dT >= 2 && dT <= 9) || dT == 12 || dT == 16 || dT == 18 || dT == 24 || dT == 27 || dT == 32;
+}
 
 // Host: descriptors and U pool of one launch; *ntiles the total tile count, *maxdt the largest slice
 // of a composed operation (0 when the launch holds one-gate operations only).
@@ -526,8 +535,10 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
     a.tmap = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(dev_blob) + dpad + ppad);
     if (maxdt == 0)
       hipLaunchKernelGGL((k_batch_layer<R, 0>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
-    else
+    else if (maxdt <= 16)
       hipLaunchKernelGGL((k_batch_layer<R, 16>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
+    else
+      hipLaunchKernelGGL((k_batch_layer<R, 32>), dim3(grid), dim3(tp.batch_block), 0, b->stream, a);
     QD_HIP(hipGetLastError());
     return QD_OK;
   }

@@ -53,7 +53,7 @@ struct TuneParams {
   int batch_wpc = 64;       // batched layer kernel: 1..63 persistent workgroups per CU, 64 one per tile
   int batch_fuse = 1;       // gates composed into one batched operation (qd_batch_apply_layers, width 0)
   int batch_spt_mid = 0;    // slices per thread of batched slices of 5..9 amplitudes (0: two load batches)
-  int batch_spt_wide = 0;   // slices per thread of batched slices of 12 or 16 amplitudes (0: as above)
+  int batch_spt_wide = 0;   // slices per thread of batched slices of 12 to 32 amplitudes (0: as above)
   int fused_cols = 64;      // slice columns per fused-block tile
   int run_min = 16;         // a target stride below this routes the gate to the LDS tile kernel
 };

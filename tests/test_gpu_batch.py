@@ -214,7 +214,7 @@ def test_fused_layers_vs_oracle(stream, width, prec):
         if prec == Q.QD_C128:
             assert max_abs(psi, ref) <= 1e-12
         else:
-            assert max_abs(psi, ref) <= 4 * len(c.gates) * 16 * U24
+            assert max_abs(psi, ref) <= 4 * len(c.gates) * 32 * U24
             assert fidelity_loss(ref, psi) <= 1e-6
 
 
@@ -293,7 +293,7 @@ def test_full_4096_circuits_at_the_tuned_width(stream):
     """The 4096-circuit, 100-layer complex64 batch at the fusion width the tuner picks, recorded as
     a graph (as the benchmark times it): every register keeps its norm; a seeded sample matches
     the oracle and the one-by-one plain path within the FP32 bound of 100 passes over slices of
-    up to 16 amplitudes."""
+    up to 32 amplitudes."""
     circs = C.config4()
     ga, L = all_layers(circs)
     b = Q.qd_batch_create([c.dims for c in circs], Q.QD_C64, stream)
@@ -312,7 +312,7 @@ def test_full_4096_circuits_at_the_tuned_width(stream):
     offs = np.cumsum([0] + [c.D for c in circs])
     p = (arena.real.astype(np.float64) ** 2 + arena.imag.astype(np.float64) ** 2)
     norms = np.add.reduceat(p, offs[:-1])
-    assert np.max(np.abs(norms - 1.0)) <= 4 * 100 * 16 * U24
+    assert np.max(np.abs(norms - 1.0)) <= 4 * 100 * 32 * U24
     rng = C.seeded_rng(84)
     sample = sorted(set(rng.choice(len(circs), 12, replace=False).tolist()) | {int(np.argmin(offs[1:] - offs[:-1]))})
     for i in sample:
@@ -321,7 +321,7 @@ def test_full_4096_circuits_at_the_tuned_width(stream):
         if c.D <= 300_000:
             assert fidelity_loss(O.run_circuit(c), psi) <= 1e-6, i
         plain = run_gpu(c, Q.QD_C64, stream)
-        assert max_abs(plain, psi) <= 4 * 100 * 16 * U24, i
+        assert max_abs(plain, psi) <= 4 * 100 * 32 * U24, i
 
 
 def test_empty_layers_are_no_ops(stream):
