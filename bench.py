@@ -676,7 +676,7 @@ def bench_batch(Q, torch, ncirc=4096, serial=True):
             "hbm_GBps_width1": 16.0 * upd / (ms1 * 1e-3) / 1e9, "one_by_one_s": one_s,
             "speedup_vs_one_by_one": one_s / (ms * 1e-3) if one_s else None, "tuned_block": block, "tuned_spt": spt,
             "tuned_grid": "one workgroup per tile" if grid >= 64 else f"{grid} workgroups per CU",
-            "tuned_spt_d5_9": spt_cls[0] or "rule", "tuned_spt_d12_16": spt_cls[1] or "rule"}
+            "tuned_spt_d5_9": spt_cls[0] or "rule", "tuned_spt_d12_32": spt_cls[1] or "rule"}
 
 
 def host_info():
