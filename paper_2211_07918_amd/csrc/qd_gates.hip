@@ -159,6 +159,56 @@ __global__ __launch_bounds__(256) void k_slices_direct(DirectArgs<R, DT, OP> a) 
     if (base[s] >= 0) mix_store<true, C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
 }
 
+// Dense gates of d_T = 12 or 16 whose targets all have strides >= run_min: one slice per thread as
+// in k_slices_direct, with U (too large for the kernel arguments in complex128) staged in LDS and
+// read by broadcast; the slice map and target offsets are staged too, before the first store.
+struct LuHead {
+  SliceMap sm;
+  int64_t toff[16];
+  // followed by 2 DT^2 values of R (U, row-major interleaved)
+};
+
+template <typename R, int DT>
+__global__ __launch_bounds__(256) void k_slices_direct_lu(R* psi_raw, const unsigned char* desc) {
+  using C = typename CxT<R>::T;
+  __shared__ R su[2 * DT * DT];
+  __shared__ SliceMap smap;
+  __shared__ int64_t st[DT];
+  static_assert(sizeof(SliceMap) % 4 == 0, "slice map copied in 4-byte words");
+  const LuHead& h = *reinterpret_cast<const LuHead*>(desc);
+  const R* ug = reinterpret_cast<const R*>(desc + sizeof(LuHead));
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < 2u * DT * DT; i += blockDim.x) su[i] = ug[i];
+  for (uint32_t i = tid; i < sizeof(SliceMap) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&smap)[i] = reinterpret_cast<const uint32_t*>(&h.sm)[i];
+  if (tid < uint32_t(DT)) st[tid] = h.toff[tid];
+  __syncthreads();
+  C* __restrict__ psi = reinterpret_cast<C*>(psi_raw);
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + tid;
+  if (i >= smap.count) return;
+  const int64_t b = sm_offset(smap, uint32_t(i));
+  C x[DT];
+#pragma unroll
+  for (int y = 0; y < DT; ++y) x[y] = ld_stream(psi + b + st[y]);
+#pragma unroll
+  for (int r = 0; r < DT; ++r) {
+    __asm__ volatile("" ::: "memory");   // U is read from LDS here (held in registers it would take hundreds)
+    R re = R(0), im = R(0);
+#pragma unroll
+    for (int c = 0; c < DT; ++c) {
+      const R ur = su[2 * (r * DT + c)], ui = su[2 * (r * DT + c) + 1];
+      re = fma(ur, x[c].x, re);
+      re = fma(-ui, x[c].y, re);
+      im = fma(ur, x[c].y, im);
+      im = fma(ui, x[c].x, im);
+    }
+    C yv;
+    yv.x = re;
+    yv.y = im;
+    st_stream(psi + b + st[r], yv);
+  }
+}
+
 // ------------------------------------------------------------------------------------------ tiled
 template <typename R, int DT, typename OP>
 struct TileArgs {
@@ -574,7 +624,16 @@ int route_gate(const Register& r, int prec, const GatePlan& p) {
   const bool mono = p.cls == QD_CLASS_MONOMIAL &&
                     (p.dT <= 9 || p.dT == 12 || p.dT == 16);
   const bool dense = p.cls != QD_CLASS_DIAGONAL && p.dT <= kMaxInlineDense;
-  if (!mono && !dense) return p.dT >= kGemmMin && p.dT <= kGemmMax ? QD_ROUTE_GEMM : QD_ROUTE_GENERIC;
+  if (!mono && !dense) {
+    if (p.dT < kGemmMin || p.dT > kGemmMax) return QD_ROUTE_GENERIC;
+    // d_T = 12 or 16 with every target stride at or above the tiling threshold: one slice per thread
+    if (p.dT == 12 || p.dT == 16) {
+      int64_t tmin = INT64_MAX;
+      for (int j = 0; j < p.k; ++j) tmin = std::min<int64_t>(tmin, r.strides[p.targets[j]]);
+      if (tmin >= tune().run_min) return QD_ROUTE_DIRECT;
+    }
+    return QD_ROUTE_GEMM;
+  }
   TileGeom g;
   return tile_geometry(r, p, prec, &g) ? QD_ROUTE_TILED : QD_ROUTE_DIRECT;
 }
@@ -746,6 +805,33 @@ static int launch_generic(qd_state* s, const GatePlan& p) {
 }
 
 template <typename R>
+static int launch_gemm(qd_state* s, const GatePlan& p);
+
+template <typename R, int DT>
+static int launch_direct_lu(qd_state* s, const GatePlan& p) {
+  const Register& r = s->reg;
+  int role[QD_MAX_QUDITS] = {};
+  for (int j = 0; j < p.k; ++j) role[p.targets[j]] = 1;
+  for (int j = 0; j < p.m; ++j) role[p.controls[j]] = 1;
+  int64_t base = 0;
+  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  const size_t bytes = sizeof(LuHead) + sizeof(R) * 2 * size_t(DT) * DT;
+  std::vector<unsigned char> buf(bytes, 0);
+  auto* h = reinterpret_cast<LuHead*>(buf.data());
+  if (fill_slicemap(make_groups(r, role, nullptr, 0, r.n), base, &h->sm) != QD_OK) return launch_gemm<R>(s, p);
+  target_offsets(r, p, h->toff);
+  R* U = reinterpret_cast<R*>(buf.data() + sizeof(LuHead));
+  for (size_t i = 0; i < 2 * size_t(DT) * DT; ++i) U[i] = R(p.U[i]);
+  if (h->sm.count == 0) return QD_OK;
+  void* dev = nullptr;
+  int rc = ring_push(s, buf.data(), bytes, &dev);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_slices_direct_lu<R, DT>), dim3(grid_for(h->sm.count, 256)), dim3(256), 0, s->stream,
+                     reinterpret_cast<R*>(s->data), static_cast<const unsigned char*>(dev));
+  return check_launch("k_slices_direct_lu");
+}
+
+template <typename R>
 static int launch_gemm(qd_state* s, const GatePlan& p) {
   const Register& r = s->reg;
   int role[QD_MAX_QUDITS] = {};
@@ -829,6 +915,8 @@ static int launch_gate_t(qd_state* s, const GatePlan& p) {
     case 7: return launch_dense_t<R, 7>(s, p);
     case 8: return launch_dense_t<R, 8>(s, p);
     case 9: return launch_dense_t<R, 9>(s, p);
+    case 12: return launch_direct_lu<R, 12>(s, p);
+    case 16: return launch_direct_lu<R, 16>(s, p);
     default: return launch_generic<R>(s, p);
   }
 }

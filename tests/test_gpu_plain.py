@@ -126,7 +126,8 @@ def test_every_route_is_exercised(stream):
         ([0], (), (), C.haar_unitary(3, rng), Q.QD_ROUTE_DIRECT),
         ([9], (), (), C.haar_unitary(2, rng), Q.QD_ROUTE_TILED),
         ([6, 9], (0,), (2,), C.haar_unitary(6, rng), Q.QD_ROUTE_TILED),
-        ([2, 0], (9,), (1,), C.haar_unitary(12, rng), Q.QD_ROUTE_GEMM),
+        ([2, 0], (9,), (1,), C.haar_unitary(12, rng), Q.QD_ROUTE_DIRECT),
+        ([2, 6], (), (), C.haar_unitary(12, rng), Q.QD_ROUTE_GEMM),
         ([9], (3,), (1,), O.z_gate(2), Q.QD_ROUTE_DIAG),
         ([2, 3], (), (), np.diag(np.exp(2j * np.pi * rng.random(12))), Q.QD_ROUTE_DIAG),
         ([1], (0,), (2,), O.x_gate(2, 1), Q.QD_ROUTE_DIRECT),
@@ -390,6 +391,31 @@ def test_gemm_route_sizes(stream, prec):
         dT = int(np.prod([dims[q] for q in t]))
         U = C.haar_unitary(dT, rng)
         assert Q.qd_gate_route(dims, prec, t, c, v, U) == (Q.QD_ROUTE_GEMM if 10 <= dT <= 64 else Q.QD_ROUTE_DIRECT), (t, dT)
+        s = Q.qd_state_init(dims, prec, stream)
+        try:
+            Q.qd_state_upload(s, psi0)
+            Q.qd_apply_gate(s, t, c, v, U)
+            out = Q.qd_state_download(s)
+        finally:
+            Q.qd_state_free(s)
+        ref = O.apply_gate(psi0, dims, t, c, v, U)
+        tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, dT)
+        assert max_abs(out, ref) <= tol, (t, c, dT, prec)
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_dense_12_16_one_slice_per_thread(stream, prec):
+    """Dense gates of d_T = 12 and 16 whose targets all have large strides run one slice per thread
+    with U in LDS (route DIRECT), with and without a control; each against the oracle."""
+    dims = (4, 3, 4, 2, 3, 2, 2, 2, 3, 2)
+    rng = C.seeded_rng(92)
+    D = O.register_size(dims)
+    psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    for t, c, v in (((0, 1), (), ()), ((1, 2), (3,), (1,)), ((0, 2), (), ()), ((2, 0), (4,), (2,))):
+        dT = int(np.prod([dims[q] for q in t]))
+        U = C.haar_unitary(dT, rng)
+        assert Q.qd_gate_route(dims, prec, t, c, v, U) == Q.QD_ROUTE_DIRECT, (t, dT)
         s = Q.qd_state_init(dims, prec, stream)
         try:
             Q.qd_state_upload(s, psi0)

@@ -133,7 +133,8 @@ def test_routes():
     assert r([9], O.z_gate(2)) == Q.QD_ROUTE_DIAG
     assert r([1], O.x_gate(3, 1), [0], [1]) == Q.QD_ROUTE_DIRECT
     assert r([1, 2], np.eye(12)[::-1]) == Q.QD_ROUTE_DIRECT        # monomial d_T = 12
-    assert r([1, 2], C.haar_unitary(12, C.seeded_rng(1))) == Q.QD_ROUTE_GEMM        # dense 10..64
+    assert r([1, 2], C.haar_unitary(12, C.seeded_rng(1))) == Q.QD_ROUTE_DIRECT      # dense 12, large strides
+    assert r([2, 6], C.haar_unitary(12, C.seeded_rng(1))) == Q.QD_ROUTE_GEMM        # dense 12, a small stride
     assert r([1, 2, 3], C.haar_unitary(36, C.seeded_rng(1))) == Q.QD_ROUTE_GEMM
     assert r([1, 2, 3, 0], C.haar_unitary(72, C.seeded_rng(1))) == Q.QD_ROUTE_GENERIC  # above 64
     assert r([1, 2, 3], np.eye(36)[::-1]) == Q.QD_ROUTE_GEMM                       # monomial, no fast case
