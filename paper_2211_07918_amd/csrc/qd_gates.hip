@@ -221,8 +221,22 @@ struct TileArgs {
   int64_t hoff[kMaxTileRuns];     // global offset of run h from the tile origin
   int64_t toff[DT];               // LDS offset of target combination y
   int64_t doff[DT];               // monomial: LDS offset of the row column y moves to
+  uint32_t nsc;                   // controls inside the suffix that the tile leaves out, and for
+  Magic32 scm[kMaxTileCtl];       // each, by increasing stride s: division by s,
+  uint32_t scmul[kMaxTileCtl];    // s (d_c - 1) and
+  uint32_t scadd[kMaxTileCtl];    // v s (v: the control value)
   OP op;
 };
+
+// Offset inside the run of the staged amplitude w: each left-out control digit is re-inserted at
+// its value, smallest stride first (w = q s + r becomes q s d_c + v s + r).
+template <typename A>
+__device__ __forceinline__ uint32_t tile_expand(const A& a, uint32_t w) {
+#pragma unroll
+  for (int j = 0; j < kMaxTileCtl; ++j)
+    if (j < int(a.nsc)) w += magic_div(w, a.scm[j]) * a.scmul[j] + a.scadd[j];
+  return w;
+}
 
 // Amplitudes a thread moves per tile: the tile holds at most 256 * kTileEpt<R> amplitudes.
 template <typename R> struct TileEpt;
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
       const uint32_t idx = tid + e * bs;
       if (idx < E) {
         const uint32_t h = magic_div(idx, a.blm);
-        const C t = ld_stream(psi + (g0 + s_hoff[h] + (idx - h * a.BL)));
+        const C t = ld_stream(psi + (g0 + s_hoff[h] + tile_expand(a, idx - h * a.BL)));
         vr[e] = t.x;
         vi[e] = t.y;
       }
@@ -294,7 +308,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
         C t;
         t.x = vr[e];
         t.y = vi[e];
-        st_stream(psi + (g0 + s_hoff[h] + (idx - h * a.BL)), t);
+        st_stream(psi + (g0 + s_hoff[h] + tile_expand(a, idx - h * a.BL)), t);
       }
     }
     if (tile + gridDim.x < a.tiles.count) __syncthreads();
@@ -575,8 +589,11 @@ static void fill_mono(const GatePlan& p, MonoOp<R, DT>* op) {
 
 // LDS tile geometry: the low suffix L = {pq, ..., n-1} of the register holds every target whose
 // stride is below run_min and is grown towards longer contiguous runs while the tile (dH runs of
-// BL amplitudes) fits the LDS budget. Returns false when no target is low
-// (the direct kernel applies) or the tile would not fit.
+// BL amplitudes) fits the LDS budget. Controls inside L (at most kMaxTileCtl; their strides are at
+// least one 128-byte line, smaller ones having been folded into the targets) are left out of the
+// tile: it stages only the amplitudes whose control digits match, so a control that falls inside
+// L costs 1/d_c of a pass as it does above L. Returns false when no target is low (the direct
+// kernel applies) or the tile would not fit.
 bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) {
   const TuneParams& tp = tune();
   int64_t min_stride = INT64_MAX;
@@ -594,27 +611,42 @@ bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) 
   const uint64_t ept = prec == QD_C128 ? TileEpt<double>::value : TileEpt<float>::value;
   const uint64_t emax = std::min<uint64_t>(uint64_t(e.tile_elems) * (prec == QD_C128 ? 1u : 2u),
                                            uint64_t(e.block) * ept);
-  bool is_t[QD_MAX_QUDITS] = {};
+  const int64_t line = prec == QD_C128 ? 8 : 16;   // amplitudes per 128-byte line
+  bool is_t[QD_MAX_QUDITS] = {}, is_c[QD_MAX_QUDITS] = {};
   for (int j = 0; j < p.k; ++j) is_t[p.targets[j]] = true;
-  int pq = low_idx;
-  uint64_t BL = uint64_t(r.strides[pq]) * r.dims[pq];
-  uint64_t dH = 1;
-  for (int i = 0; i < pq; ++i)
-    if (is_t[i]) dH *= r.dims[i];
-  while (pq > 0) {
-    const int q = pq - 1;
-    const uint64_t nBL = BL * r.dims[q];
-    const uint64_t ndH = is_t[q] ? dH / r.dims[q] : dH;
-    if (nBL * ndH > emax) break;
-    pq = q;
-    BL = nBL;
-    dH = ndH;
-  }
-  if (dH > uint64_t(kMaxTileRuns) || BL * dH > emax) return false;
-  g->pq = pq;
-  g->BL = BL;
-  g->dH = dH;
-  return true;
+  for (int j = 0; j < p.m; ++j) is_c[p.controls[j]] = r.strides[p.controls[j]] >= line;
+  auto grow = [&](bool compact) -> bool {
+    int pq = low_idx, nsc = 0;
+    uint64_t BL = 1, dH = 1;
+    for (int i = pq; i < r.n; ++i) {
+      if (compact && is_c[i]) ++nsc;
+      else BL *= uint64_t(r.dims[i]);
+    }
+    if (nsc > kMaxTileCtl) return false;
+    for (int i = 0; i < pq; ++i)
+      if (is_t[i]) dH *= r.dims[i];
+    while (pq > 0) {
+      const int q = pq - 1;
+      const bool drop = compact && is_c[q];
+      if (drop && nsc == kMaxTileCtl) break;
+      const uint64_t nBL = drop ? BL : BL * r.dims[q];
+      const uint64_t ndH = is_t[q] ? dH / r.dims[q] : dH;
+      if (nBL * ndH > emax) break;
+      pq = q;
+      BL = nBL;
+      dH = ndH;
+      nsc += drop ? 1 : 0;
+    }
+    if (dH > uint64_t(kMaxTileRuns) || BL * dH > emax) return false;
+    g->pq = pq;
+    g->BL = BL;
+    g->dH = dH;
+    g->nsc = 0;
+    for (int i = r.n - 1; i >= pq && compact; --i)
+      if (is_c[i]) g->sc[g->nsc++] = i;
+    return true;
+  };
+  return grow(true) || grow(false);
 }
 
 int route_gate(const Register& r, int prec, const GatePlan& p) {
@@ -666,15 +698,36 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       a.BL = uint32_t(BL);
       a.dH = uint32_t(dH);
       a.blm = make_magic32(uint32_t(BL));
+      // LDS strides of the suffix: the register's, with the left-out controls' digits removed
+      bool out[QD_MAX_QUDITS] = {};
+      for (int j = 0; j < tg.nsc; ++j) out[tg.sc[j]] = true;
+      Register lr = r;
+      {
+        int64_t st = 1;
+        for (int i = r.n - 1; i >= pq; --i) {
+          lr.strides[i] = st;
+          if (!out[i]) st *= r.dims[i];
+        }
+      }
       int64_t tbase = 0, ibase = 0;
       for (int j = 0; j < p.m; ++j) {
         const int c = p.controls[j];
         if (c < pq) tbase += int64_t(p.cvals[j]) * r.strides[c];
-        else ibase += int64_t(p.cvals[j]) * r.strides[c];
+        else if (!out[c]) ibase += int64_t(p.cvals[j]) * lr.strides[c];
+      }
+      a.nsc = uint32_t(tg.nsc);
+      for (int j = 0; j < tg.nsc; ++j) {
+        const int c = tg.sc[j];
+        int v = 0;
+        for (int q = 0; q < p.m; ++q)
+          if (p.controls[q] == c) v = p.cvals[q];
+        a.scm[j] = make_magic32(uint32_t(r.strides[c]));
+        a.scmul[j] = uint32_t(r.strides[c] * (r.dims[c] - 1));
+        a.scadd[j] = uint32_t(int64_t(v) * r.strides[c]);
       }
       int rc = fill_slicemap(make_groups(r, role, nullptr, 0, pq), tbase, &a.tiles);
       if (rc) return rc;
-      rc = fill_slicemap(make_groups(r, role, nullptr, pq, r.n), ibase, &a.inner);
+      rc = fill_slicemap(make_groups(lr, role, nullptr, pq, r.n), ibase, &a.inner);
       if (rc) return rc;
       // run offsets: h in mixed radix over the high targets in listed order
       int hmul[QD_MAX_QUDITS] = {};
@@ -699,7 +752,7 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
           const int t = p.targets[j];
           const int dg = rem % r.dims[t];
           rem /= r.dims[t];
-          off += t < pq ? int64_t(dg) * hmul[j] * int64_t(BL) : int64_t(dg) * r.strides[t];
+          off += t < pq ? int64_t(dg) * hmul[j] * int64_t(BL) : int64_t(dg) * lr.strides[t];
         }
         a.toff[y] = off;
       }

@@ -17,6 +17,7 @@ constexpr int kMaxGroups = 12;      // free-qudit groups a fast-path descriptor 
 constexpr int kMaxInlineDense = 9;  // dense U travels inside the kernel arguments up to d_T = 9
 constexpr int kMaxInlineTable = 64; // diagonal / monomial tables inline up to d_T = 64
 constexpr int kMaxTileRuns = 16;    // runs per LDS tile (product of the high targets' dims)
+constexpr int kMaxTileCtl = 2;      // controls inside an LDS tile's suffix that the tile leaves out
 
 // ------------------------------------------------------------------------------------------ errors
 int fail(int code, const std::string& msg);   // records msg for qd_last_error, returns code
@@ -160,8 +161,10 @@ void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, c
 
 struct TileGeom {
   int pq = 0;          // first qudit of the low suffix staged in LDS
-  uint64_t BL = 0;     // run length
+  uint64_t BL = 0;     // run length (amplitudes staged per run)
   uint64_t dH = 0;     // number of runs
+  int nsc = 0;         // controls inside the suffix left out of the tile ...
+  int sc[kMaxTileCtl] = {};  // ... their qudits, by increasing stride
 };
 bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g);
 int route_gate(const Register& r, int prec, const GatePlan& p);

@@ -426,3 +426,48 @@ def test_dense_12_16_one_slice_per_thread(stream, prec):
         ref = O.apply_gate(psi0, dims, t, c, v, U)
         tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, dT)
         assert max_abs(out, ref) <= tol, (t, c, dT, prec)
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+@pytest.mark.parametrize("tile_elems", [256, 0, 4096])
+def test_tiled_controls_inside_the_suffix(stream, prec, tile_elems):
+    """Low-stride targets whose controls sit inside the LDS tile's contiguous suffix: controls of at
+    least one 128-byte line of stride are left out of the tile (one or two of them, a third stays
+    outside the tile), a control below one line stays inside it, each case against the oracle."""
+    dims = (3, 2, 2, 4, 2, 3, 2, 2, 3, 2, 3)          # strides 6912 ... 18, 6, 3, 1
+    rng = C.seeded_rng(93)
+    D = O.register_size(dims)
+    psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    cases = [
+        ((10,), (7,), (1,)),                 # control stride 18: not a whole number of lines
+        ((10,), (6,), (0,)),                 # stride 36
+        ((9,), (7, 5), (1, 2)),              # two controls inside the suffix
+        ((10,), (7, 6, 5), (0, 1, 1)),       # three: the third stays above the tile
+        ((10, 4), (7,), (1,)),               # a high target (two runs per tile) and a control inside
+        ((8,), (4, 2), (1, 0)),              # controls of strides 216 and 1728
+    ]
+    dims9 = (2, 3, 2, 4, 2, 9, 3)                     # a 9-level target over a qutrit of stride 1
+    D9 = O.register_size(dims9)
+    psi9 = rng.standard_normal(D9) + 1j * rng.standard_normal(D9)
+    psi9 /= np.linalg.norm(psi9)
+    cases9 = [((5,), (6,), (2,)), ((5,), (6, 3), (1, 2)), ((5,), (3, 6), (0, 0))]
+    Q.qd_tune_set(Q.QD_TUNE_TILE_ELEMS, tile_elems)
+    try:
+        for reg, x0, cs in ((dims, psi0, cases), (dims9, psi9, cases9)):
+            for t, c, v in cs:
+                dT = int(np.prod([reg[q] for q in t]))
+                for U in (C.haar_unitary(dT, rng), O.x_gate(dT, 1) if len(t) == 1 else np.eye(dT)[::-1]):
+                    assert Q.qd_gate_route(reg, prec, t, c, v, U) == Q.QD_ROUTE_TILED, (reg, t, c)
+                    s = Q.qd_state_init(reg, prec, stream)
+                    try:
+                        Q.qd_state_upload(s, x0)
+                        Q.qd_apply_gate(s, t, c, v, U)
+                        out = Q.qd_state_download(s)
+                    finally:
+                        Q.qd_state_free(s)
+                    ref = O.apply_gate(x0, reg, t, c, v, U)
+                    tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, dT)
+                    assert max_abs(out, ref) <= tol, (reg, t, c, prec, tile_elems)
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_TILE_ELEMS, 0)
