@@ -259,12 +259,17 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
   __syncthreads();
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = sm_offset(a.tiles, tile);
+    // The per-element run and LDS indices are recomputed in the load and in the store stage from
+    // opaque copies of the thread index: kept live across the LDS mix they would take about
+    // 3 EPT registers and cut the workgroups per CU for the wider gates.
+    uint32_t tl = tid;
+    __asm__ volatile("" : "+v"(tl));
     // every load of the tile is issued before the first LDS write
     // (real and imaginary parts in separate scalar arrays so they stay in registers)
     R vr[EPT], vi[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const uint32_t idx = tid + e * bs;
+      const uint32_t idx = tl + e * bs;
       if (idx < E) {
         const uint32_t h = magic_div(idx, a.blm);
         const C t = ld_stream(psi + (g0 + s_hoff[h] + tile_expand(a, idx - h * a.BL)));
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const uint32_t idx = tid + e * bs;
+      const uint32_t idx = tl + e * bs;
       if (idx < E) {
         C t;
         t.x = vr[e];
@@ -291,9 +296,11 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
       mix_store<false, C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
     }
     __syncthreads();
+    uint32_t ts = tid;
+    __asm__ volatile("" : "+v"(ts));
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const uint32_t idx = tid + e * bs;
+      const uint32_t idx = ts + e * bs;
       if (idx < E) {
         const C t = lds[idx];
         vr[e] = t.x;
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const uint32_t idx = tid + e * bs;
+      const uint32_t idx = ts + e * bs;
       if (idx < E) {
         const uint32_t h = magic_div(idx, a.blm);
         C t;
@@ -759,7 +766,8 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       fill_doff<DT>(p, a.toff, a.doff);
       if (a.tiles.count == 0 || a.inner.count == 0) return QD_OK;
       const size_t lds = size_t(BL * dH) * sizeof(R) * 2;
-      const unsigned grid = a.tiles.count;
+      // workgroups walk the tiles; at most 2^22 of them keep the grid inside 32-bit work-item counts
+      const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(1) << 22));
       hipLaunchKernelGGL((k_slices_tiled<R, DT, OP>), dim3(grid), dim3(ent.block), lds, s->stream, a);
       return check_launch("k_slices_tiled");
     }
