@@ -225,8 +225,16 @@ struct TileArgs {
   Magic32 scm[kMaxTileCtl];       // each, by increasing stride s: division by s,
   uint32_t scmul[kMaxTileCtl];    // s (d_c - 1) and
   uint32_t scadd[kMaxTileCtl];    // v s (v: the control value)
+  const void* ug;                 // dense d_T >= kTileLdsU: U in device memory (staged in LDS)
   OP op;
 };
+
+// Dense gates of d_T >= 5 read U from LDS in the tile kernel: inside the kernel arguments its
+// 2 d_T^2 values overflow the scalar registers, and the mix then spends more instructions reading
+// them back than multiplying.
+constexpr int kTileLdsU = 5;
+template <typename OP> struct DenseDim { static constexpr int value = 0; };
+template <typename R, int DT> struct DenseDim<DenseOp<R, DT>> { static constexpr int value = DT; };
 
 // Offset inside the run of the staged amplitude w: each left-out control digit is re-inserted at
 // its value, smallest stride first (w = q s + r becomes q s d_c + v s + r).
@@ -247,8 +255,10 @@ template <typename R, int DT, typename OP>
 __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
   using C = typename CxT<R>::T;
   constexpr int EPT = TileEpt<R>::value;
+  constexpr int kUL = DenseDim<OP>::value >= kTileLdsU ? 2 * DT * DT : 0;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int64_t s_hoff[kMaxTileRuns];
+  __shared__ R su[kUL > 0 ? kUL : 1];
   C* lds = reinterpret_cast<C*>(lds_raw);
   C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
   const uint32_t bs = blockDim.x, tid = threadIdx.x;
@@ -256,6 +266,10 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
 #pragma unroll
   for (int h = 0; h < kMaxTileRuns; ++h)
     if (int(tid) == h) s_hoff[h] = a.hoff[h];
+  if constexpr (kUL > 0) {
+    const R* ug = static_cast<const R*>(a.ug);
+    for (uint32_t i = tid; i < uint32_t(kUL); i += bs) su[i] = ug[i];
+  }
   __syncthreads();
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = sm_offset(a.tiles, tile);
@@ -293,7 +307,27 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
       C x[DT];
 #pragma unroll
       for (int y = 0; y < DT; ++y) x[y] = lds[b + a.toff[y]];
-      mix_store<false, C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
+      if constexpr (kUL > 0) {
+#pragma unroll
+        for (int r = 0; r < DT; ++r) {
+          __asm__ volatile("" ::: "memory");   // U is read from LDS row by row, not held in registers
+          R re = R(0), im = R(0);
+#pragma unroll
+          for (int c = 0; c < DT; ++c) {
+            const R ur = su[2 * (r * DT + c)], ui = su[2 * (r * DT + c) + 1];
+            re = fma(ur, x[c].x, re);
+            re = fma(-ui, x[c].y, re);
+            im = fma(ur, x[c].y, im);
+            im = fma(ui, x[c].x, im);
+          }
+          C yv;
+          yv.x = re;
+          yv.y = im;
+          lds[b + a.toff[r]] = yv;
+        }
+      } else {
+        mix_store<false, C, R, DT>(lds, b, a.toff, a.doff, a.op, x);
+      }
     }
     __syncthreads();
     uint32_t ts = tid;
@@ -765,6 +799,12 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       }
       fill_doff<DT>(p, a.toff, a.doff);
       if (a.tiles.count == 0 || a.inner.count == 0) return QD_OK;
+      if constexpr (DenseDim<OP>::value >= kTileLdsU) {
+        void* dev = nullptr;
+        rc = ring_push(s, op.u, sizeof(op.u), &dev);
+        if (rc) return rc;
+        a.ug = dev;
+      }
       const size_t lds = size_t(BL * dH) * sizeof(R) * 2;
       // workgroups walk the tiles; at most 2^22 of them keep the grid inside 32-bit work-item counts
       const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(1) << 22));
