@@ -225,14 +225,14 @@ struct TileArgs {
   Magic32 scm[kMaxTileCtl];       // each, by increasing stride s: division by s,
   uint32_t scmul[kMaxTileCtl];    // s (d_c - 1) and
   uint32_t scadd[kMaxTileCtl];    // v s (v: the control value)
-  const void* ug;                 // dense d_T >= kTileLdsU: U in device memory (staged in LDS)
+  const void* ug;                 // dense gates: U in device memory (staged in LDS)
   OP op;
 };
 
-// Dense gates of d_T >= 5 read U from LDS in the tile kernel: inside the kernel arguments its
-// 2 d_T^2 values overflow the scalar registers, and the mix then spends more instructions reading
-// them back than multiplying.
-constexpr int kTileLdsU = 5;
+// Dense gates read U from LDS in the tile kernel: inside the kernel arguments its 2 d_T^2 values
+// join the slice maps in the scalar registers, which overflow, and the mix then spends more
+// instructions reading spilled values back than multiplying.
+constexpr int kTileLdsU = 2;
 template <typename OP> struct DenseDim { static constexpr int value = 0; };
 template <typename R, int DT> struct DenseDim<DenseOp<R, DT>> { static constexpr int value = DT; };
 
