@@ -225,13 +225,13 @@ struct TileArgs {
   Magic32 scm[kMaxTileCtl];       // each, by increasing stride s: division by s,
   uint32_t scmul[kMaxTileCtl];    // s (d_c - 1) and
   uint32_t scadd[kMaxTileCtl];    // v s (v: the control value)
-  const void* ug;                 // dense gates: U in device memory (staged in LDS)
   OP op;
 };
 
-// Dense gates read U from LDS in the tile kernel: inside the kernel arguments its 2 d_T^2 values
-// join the slice maps in the scalar registers, which overflow, and the mix then spends more
-// instructions reading spilled values back than multiplying.
+// Dense gates read U from LDS in the tile kernel. Left to the compiler, its 2 d_T^2 values join the
+// slice maps in the scalar registers, which overflow, and the mix then spends more instructions
+// reading spilled values back than multiplying. Each workgroup copies U from the kernel argument
+// segment (one vector load per thread, no upload) into LDS before its first tile.
 constexpr int kTileLdsU = 2;
 template <typename OP> struct DenseDim { static constexpr int value = 0; };
 template <typename R, int DT> struct DenseDim<DenseOp<R, DT>> { static constexpr int value = DT; };
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_slices_tiled(TileArgs<R, DT, OP> a) {
   for (int h = 0; h < kMaxTileRuns; ++h)
     if (int(tid) == h) s_hoff[h] = a.hoff[h];
   if constexpr (kUL > 0) {
-    const R* ug = static_cast<const R*>(a.ug);
+    const R* ug = a.op.u;   // read in place from the kernel argument segment
     for (uint32_t i = tid; i < uint32_t(kUL); i += bs) su[i] = ug[i];
   }
   __syncthreads();
@@ -799,12 +799,6 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       }
       fill_doff<DT>(p, a.toff, a.doff);
       if (a.tiles.count == 0 || a.inner.count == 0) return QD_OK;
-      if constexpr (DenseDim<OP>::value >= kTileLdsU) {
-        void* dev = nullptr;
-        rc = ring_push(s, op.u, sizeof(op.u), &dev);
-        if (rc) return rc;
-        a.ug = dev;
-      }
       const size_t lds = size_t(BL * dH) * sizeof(R) * 2;
       // workgroups walk the tiles; at most 2^22 of them keep the grid inside 32-bit work-item counts
       const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(1) << 22));
