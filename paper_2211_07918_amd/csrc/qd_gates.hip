@@ -820,9 +820,11 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   fill_doff<DT>(p, a.toff, a.doff);
   if (a.sm.count == 0) return QD_OK;
   const int bs = ent.block;
+  // Several slices per thread only up to d_T = 4: beyond, two slices' operands and the gate's
+  // kernel arguments overflow the scalar registers and the spilled values are read back per FMA.
   if (ent.spt >= 4 && DT <= 4) {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 4>), dim3(grid_for(a.sm.count, uint64_t(bs) * 4)), dim3(bs), 0, s->stream, a);
-  } else if (ent.spt >= 2) {
+  } else if (ent.spt >= 2 && DT <= 4) {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
   } else {
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0, s->stream, a);
