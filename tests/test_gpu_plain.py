@@ -471,3 +471,44 @@ def test_tiled_controls_inside_the_suffix(stream, prec, tile_elems):
                     assert max_abs(out, ref) <= tol, (reg, t, c, prec, tile_elems)
     finally:
         Q.qd_tune_set(Q.QD_TUNE_TILE_ELEMS, 0)
+
+
+def test_tiled_kernel_walks_tiles_beyond_the_grid_cap(stream):
+    """A launch of more than 2^22 LDS tiles: the workgroups (at most 2^22) each walk two tiles. The
+    register (23 qubits, a 200-level qudit, a qubit; D = 3,355,443,200, 54 GB per complex128 state)
+    with a 512-amplitude tile budget stages runs of 2 x 200 = 400 amplitudes for a gate on the last
+    qubit, so the launch covers D / 400 = 8,388,608 tiles. The same gate through the direct kernel
+    (run_min 1) on an identical state is the reference; both sides do the same FP64 arithmetic."""
+    dims = (2,) * 23 + (200, 2)
+    n = len(dims)
+    D = O.register_size(dims)
+    assert D == 3355443200 and D // 400 > 2 ** 22
+    rng = C.seeded_rng(94)
+    V = C.haar_unitary(2, rng)
+    prep = [((0,), C.haar_unitary(2, rng)), ((11,), C.haar_unitary(2, rng)), ((22,), C.haar_unitary(2, rng)),
+            ((n - 1,), C.haar_unitary(2, rng))]
+    states = []
+    try:
+        for _ in range(2):
+            s = Q.qd_state_init(dims, Q.QD_C128, stream)
+            states.append(s)
+            Q.qd_state_set_basis(s, [0] * n)
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 1)
+        try:
+            for s in states:
+                for t, U in prep:
+                    Q.qd_apply_gate(s, t, (), (), U)
+            Q.qd_apply_gate(states[1], (n - 1,), (), (), V)           # direct kernel
+        finally:
+            Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)
+        Q.qd_tune_set(Q.QD_TUNE_TILE_ELEMS, 512)
+        try:
+            assert Q.qd_gate_route(dims, Q.QD_C128, (n - 1,), (), (), V) == Q.QD_ROUTE_TILED
+            Q.qd_apply_gate(states[0], (n - 1,), (), (), V)           # tile kernel, 8.4M tiles
+        finally:
+            Q.qd_tune_set(Q.QD_TUNE_TILE_ELEMS, 0)
+        err, fid, drift = Q.qd_compare(states[1], states[0])
+        assert err <= 1e-12 and abs(fid) <= 1e-12 and drift <= 1e-12, (err, fid, drift)
+    finally:
+        for s in states:
+            Q.qd_state_free(s)
