@@ -489,7 +489,7 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
     # passes, as qd_density_apply_ops forms them: a run of consecutive operations on the same
     # targets with no controls and d_T <= 4 is one composed pass over all D^2 elements; any other
     # channel is one pass; any other gate is one pass when its embedding on targets and controls
-    # has d_G <= 4 (d_G <= 3 for a dense U with controls), else two, each touching the D^2 / d_c
+    # has d_G <= 4 (d_G <= 3 for a controlled U that is not diagonal), else two, each touching the D^2 / d_c
     # elements whose control digits match
     def fusable(o):
         t = o[1].targets if o[0] == "gate" else (o[1],)
@@ -510,8 +510,8 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
             g = ops[i][1]
             dc = int(np.prod([dims[c] for c in g.controls])) if g.controls else 1
             dG = int(np.prod([dims[q] for q in g.targets])) * dc
-            dense = Q.qd_gate_class(Q.gate_unitary(g, dims)) == Q.QD_CLASS_DENSE
-            fused = dG <= (3 if dense and g.controls else 4)
+            diag = Q.qd_gate_class(Q.gate_unitary(g, dims)) == Q.QD_CLASS_DIAGONAL
+            fused = dG <= (3 if g.controls and not diag else 4)
             passes += 1 if fused else 2
             active += D * D if fused else 2 * (D * D // dc)
         i = j

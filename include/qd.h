@@ -451,9 +451,9 @@ int qd_density_from_state(qd_state* rho, const qd_state* psi);
 
 /* rho -> G rho G^dagger for the (controlled) gate of qd_apply_gate_ex on the physical register
  * (targets and controls are 0..n-1; validation and flags as there). With G embedded on its targets
- * and controls (d_G = d_T x prod d_c), a gate with d_G <= 4 (d_G <= 3 for a dense U with
- * controls) is one pass of G (x) conj(G) on (T, C, T + n, C + n); others are two passes (U on T,
- * conj(U) on T + n with controls c + n).
+ * and controls (d_G = d_T x prod d_c), a gate with d_G <= 4 (d_G <= 3 for a dense or a monomial
+ * non-diagonal U with controls) is one pass of G (x) conj(G) on (T, C, T + n, C + n); others are
+ * two passes (U on T, conj(U) on T + n with controls c + n).
  * Asynchronous. */
 int qd_density_apply_gate(qd_state* rho, const int32_t* targets, int32_t k, const int32_t* controls,
                           const int32_t* control_values, int32_t m, const double* U, uint32_t flags);
