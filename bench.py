@@ -486,22 +486,26 @@ def bench_density(Q, torch, reps=3, cpu_seconds=10.0, cpu=True):
     circ, ops = _noisy_ops(C, dims, 60, 1008)
     kraus = {d: Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, d, 1e-3) for d in set(dims)}
     lib_ops = [o if o[0] == "gate" else ("chan", (o[1],), kraus[dims[o[1]]]) for o in ops]
-    # passes, as qd_density_apply_ops forms them: a run of consecutive operations on the same
-    # targets with no controls and d_T <= 4 is one composed pass over all D^2 elements; any other
-    # channel is one pass; any other gate is one pass when its embedding on targets and controls
-    # has d_G <= 4 (d_G <= 3 for a controlled U that is not diagonal), else two, each touching the D^2 / d_c
-    # elements whose control digits match
-    def fusable(o):
-        t = o[1].targets if o[0] == "gate" else (o[1],)
-        ctl = o[1].controls if o[0] == "gate" else ()
-        return (not ctl and int(np.prod([dims[q] for q in t])) <= 4), tuple(t)
+    # passes, as qd_density_apply_ops forms them: a run of consecutive operations whose targets and
+    # controls together span qudits of dimension <= 4 is one composed pass over all D^2 elements;
+    # any other channel is one pass; any other gate is one pass when its embedding on targets and
+    # controls has d_G <= 4 (d_G <= 3 for a controlled U that is not diagonal), else two, each
+    # touching the D^2 / d_c elements whose control digits match
+    def support(o):
+        if o[0] == "gate":
+            return set(o[1].targets) | set(o[1].controls)
+        return {o[1]}
+
+    def span(qs):
+        return int(np.prod([dims[q] for q in qs]))
 
     passes, active, i = 0, 0, 0
     while i < len(ops):
-        f, t = fusable(ops[i])
+        S = support(ops[i])
         j = i + 1
-        if f:
-            while j < len(ops) and fusable(ops[j]) == (True, t):
+        if span(S) <= 4:
+            while j < len(ops) and span(S | support(ops[j])) <= 4:
+                S |= support(ops[j])
                 j += 1
         if j - i > 1 or ops[i][0] == "chan":
             passes += 1

@@ -491,9 +491,11 @@ typedef struct {
 } qd_density_op;
 
 /* Apply count operations in order, as qd_density_apply_gate / qd_density_apply_channel would, with
- * every operation validated first. Consecutive operations on the same target list without controls
- * and with d_T <= 4 (a gate and the channels that follow it, say) are composed on the host in FP64
- * into one superoperator and applied in one pass. Asynchronous. */
+ * every operation validated first. A run of two or more consecutive operations whose targets and
+ * controls together span qudits S with prod d_S <= 4 (a gate and the channels that follow it, a
+ * qubit-controlled gate on a qubit and its channel, operations on two qubits) is composed on the
+ * host in FP64: each operation embedded on S (a gate as its controlled unitary, the identity
+ * elsewhere), then one pass of the product superoperator on (S, S + n). Asynchronous. */
 int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count, uint32_t flags);
 
 /* tr(rho) (both parts), fixed reduction order. Synchronises. */

@@ -12,7 +12,10 @@
 //     G (x) conj(G) over (T, C, T + n, C + n); other gates take two passes (U on T with its
 //     controls, conj(U) on T + n with the shifted controls);
 //   * a channel with Kraus operators K_1..K_r maps rho -> sum_k K_k rho K_k^dagger, one pass of the
-//     superoperator S = sum_k K_k (x) conj(K_k) over (T, T + n).
+//     superoperator S = sum_k K_k (x) conj(K_k) over (T, T + n);
+//   * consecutive operations whose targets and controls together span qudits Sq of dimension
+//     <= kFuseGroup are composed on the host into one superoperator on (Sq, Sq + n), each embedded
+//     on Sq, and applied in one pass.
 // Both run through the library's gate kernels (HBM-bound passes over the D^2 elements). The
 // readouts here (outer product, diagonal, trace, <psi|rho|psi>) are HBM-bound kernels of their own.
 #include <hip/hip_runtime.h>
@@ -41,7 +44,7 @@ constexpr int kFuseGateFree = 4;      // dense U without controls
 constexpr int kFuseMono = 4;          // diagonal U, or monomial U without controls
 constexpr int kFuseMonoCtl = 3;       // monomial U with controls
 constexpr int kMaxChannelDim = 32;    // d_T of a channel (its superoperator is d_T^2 x d_T^2 <= 1024)
-constexpr int kFuseGroup = 4;         // d_T up to which a run of operations on the same targets is one pass
+constexpr int kFuseGroup = 4;         // dimension of the qudits a run of operations touches, up to which it is one pass
 constexpr int kRedGrid = 1024;
 
 template <typename R> struct Cx;
@@ -182,6 +185,60 @@ static std::vector<double> superoperator(const double* kraus, int32_t nk, int dT
           }
   }
   return S;
+}
+
+// The matrices of an operation on the qudit list Sq (first most significant): a gate's controlled
+// unitary (U on its targets where its controls hold their values, the identity elsewhere) or each
+// Kraus matrix of a channel, times the identity on the other qudits of Sq.
+static std::vector<double> embed_on(const Register& phys, const qd_density_op& o, const std::vector<int>& Sq) {
+  const int ns = int(Sq.size());
+  int dS = 1, dT = 1;
+  for (int q : Sq) dS *= phys.dims[q];
+  for (int j = 0; j < o.k; ++j) dT *= phys.dims[o.targets[j]];
+  const int nk = o.kind == QD_OP_GATE ? 1 : o.nk;
+  const int m = o.kind == QD_OP_GATE ? o.m : 0;
+  std::vector<int> tpos(o.k), tmul(o.k), cpos(m);
+  auto pos_of = [&](int q) { return int(std::find(Sq.begin(), Sq.end(), q) - Sq.begin()); };
+  for (int j = o.k - 1, mul = 1; j >= 0; --j) {
+    tpos[j] = pos_of(o.targets[j]);
+    tmul[j] = mul;
+    mul *= phys.dims[o.targets[j]];
+  }
+  for (int j = 0; j < m; ++j) cpos[j] = pos_of(o.controls[j]);
+  std::vector<char> is_t(ns, 0);
+  for (int j = 0; j < o.k; ++j) is_t[tpos[j]] = 1;
+  std::vector<double> W(2 * size_t(nk) * dS * dS, 0.0);
+  std::vector<int> dx(ns), dy(ns);
+  for (int x = 0; x < dS; ++x)
+    for (int y = 0; y < dS; ++y) {
+      for (int s = ns - 1, rx = x, ry = y; s >= 0; --s) {
+        dx[s] = rx % phys.dims[Sq[s]];
+        dy[s] = ry % phys.dims[Sq[s]];
+        rx /= phys.dims[Sq[s]];
+        ry /= phys.dims[Sq[s]];
+      }
+      bool same = true;                   // every digit the operation does not act on is kept
+      for (int s = 0; s < ns; ++s) same = same && (is_t[s] || dx[s] == dy[s]);
+      if (!same) continue;
+      bool on = true;
+      for (int j = 0; j < m; ++j) on = on && dy[cpos[j]] == o.control_values[j];
+      int tx = 0, ty = 0;
+      for (int j = 0; j < o.k; ++j) {
+        tx += dx[tpos[j]] * tmul[j];
+        ty += dy[tpos[j]] * tmul[j];
+      }
+      for (int kk = 0; kk < nk; ++kk) {
+        const size_t w = 2 * (size_t(kk) * dS * dS + size_t(x) * dS + y);
+        if (on) {
+          const double* K = o.mats + 2 * size_t(kk) * dT * dT;
+          W[w] = K[2 * (tx * dT + ty)];
+          W[w + 1] = K[2 * (tx * dT + ty) + 1];
+        } else if (tx == ty) {
+          W[w] = 1.0;
+        }
+      }
+    }
+  return W;
 }
 
 }  // namespace dm
@@ -437,24 +494,32 @@ int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count,
     if (rc) return rc;
   }
   const uint32_t skip = flags | QD_FLAG_SKIP_UNITARY_CHECK;
-  auto dim_of = [&](const qd_density_op& o) {
-    int d = 1;
-    for (int j = 0; j < o.k; ++j) d *= phys.dims[o.targets[j]];
-    return d;
+  // the sorted union of a list of qudits and an operation's targets and controls
+  auto with_support = [&](std::vector<int> sq, const qd_density_op& o) {
+    for (int j = 0; j < o.k; ++j) sq.push_back(o.targets[j]);
+    if (o.kind == QD_OP_GATE)
+      for (int j = 0; j < o.m; ++j) sq.push_back(o.controls[j]);
+    std::sort(sq.begin(), sq.end());
+    sq.erase(std::unique(sq.begin(), sq.end()), sq.end());
+    return sq;
   };
-  auto fusable = [&](const qd_density_op& o) { return o.m == 0 && dim_of(o) <= kFuseGroup; };
-  auto same_targets = [&](const qd_density_op& a, const qd_density_op& b) {
-    if (a.k != b.k) return false;
-    for (int j = 0; j < a.k; ++j)
-      if (a.targets[j] != b.targets[j]) return false;
-    return true;
+  auto dim_of_set = [&](const std::vector<int>& sq) {
+    int d = 1;
+    for (int q : sq) d *= phys.dims[q];
+    return d;
   };
   int32_t i = 0;
   while (i < count) {
     const qd_density_op& o = ops[i];
+    std::vector<int> Sq = with_support({}, o);
     int32_t e = i + 1;
-    if (fusable(o))
-      while (e < count && fusable(ops[e]) && same_targets(ops[e], o)) ++e;
+    if (dim_of_set(Sq) <= kFuseGroup)
+      while (e < count) {
+        std::vector<int> U2 = with_support(Sq, ops[e]);
+        if (dim_of_set(U2) > kFuseGroup) break;
+        Sq.swap(U2);
+        ++e;
+      }
     if (e - i == 1) {
       rc = o.kind == QD_OP_GATE
                ? qd_density_apply_gate(rho, o.targets, o.k, o.controls, o.control_values, o.m, o.mats, skip)
@@ -463,14 +528,15 @@ int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count,
       i = e;
       continue;
     }
-    // compose S = S_{e-1} ... S_i in FP64: a gate contributes U (x) conj(U), a channel
-    // sum_k K_k (x) conj(K_k)
-    const int dT = dim_of(o), N = dT * dT;
+    // compose S = S_{e-1} ... S_i in FP64 on the run's qudits Sq: a gate contributes W (x) conj(W),
+    // a channel sum_k W_k (x) conj(W_k), with W its matrices embedded on Sq
+    const int dT = dim_of_set(Sq), N = dT * dT;
     std::vector<double> S(2 * size_t(N) * N, 0.0), T, P(2 * size_t(N) * N);
     for (int r = 0; r < N; ++r) S[2 * (size_t(r) * N + r)] = 1.0;
     for (int32_t q = i; q < e; ++q) {
       const qd_density_op& g = ops[q];
-      T = superoperator(g.mats, g.kind == QD_OP_GATE ? 1 : g.nk, dT);
+      const std::vector<double> W = embed_on(phys, g, Sq);
+      T = superoperator(W.data(), g.kind == QD_OP_GATE ? 1 : g.nk, dT);
       // P = T * S
       for (int r = 0; r < N; ++r)
         for (int c = 0; c < N; ++c) {
@@ -486,9 +552,9 @@ int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count,
         }
       S.swap(P);
     }
-    std::vector<int32_t> t2(o.targets, o.targets + o.k);
-    for (int j = 0; j < o.k; ++j) t2.push_back(o.targets[j] + n);
-    rc = qd_apply_gate_ex(rho, t2.data(), 2 * o.k, nullptr, nullptr, 0, S.data(), QD_FLAG_SKIP_UNITARY_CHECK);
+    std::vector<int32_t> t2(Sq.begin(), Sq.end());
+    for (int q : Sq) t2.push_back(q + n);
+    rc = qd_apply_gate_ex(rho, t2.data(), int32_t(t2.size()), nullptr, nullptr, 0, S.data(), QD_FLAG_SKIP_UNITARY_CHECK);
     if (rc) return rc;
     i = e;
   }

@@ -235,3 +235,46 @@ def test_operation_sequences_fuse_and_match(stream):
     finally:
         Q.qd_state_free(a)
         Q.qd_state_free(b)
+
+
+def test_runs_across_targets_compose_and_match(stream):
+    """Consecutive operations whose targets and controls together span qudits of dimension <= 4 (two
+    qubits here) are one composed pass: controlled shifts, a controlled phase, a controlled dense
+    gate, channels on either qubit and gates on the other, each run embedded on the pair. Against
+    the oracle and against the same operations applied one call at a time."""
+    rng = np.random.default_rng(32)
+    dims = (2, 3, 2, 2)
+    G = C.Gate
+    dep = lambda d, p: Q.qd_channel_kraus(Q.QD_CHANNEL_DEPOLARIZING, d, p)
+    amp = lambda d, p: Q.qd_channel_kraus(Q.QD_CHANNEL_AMPLITUDE_DAMPING, d, p)
+    ops = [("gate", G("U", (0,), U=C.haar_unitary(2, rng))), ("gate", G("U", (1,), U=C.haar_unitary(3, rng))),
+           ("gate", G("U", (3,), U=C.haar_unitary(2, rng))),
+           ("gate", G("X", (0,), (2,), (1,), a=1)), ("chan", (0,), dep(2, 0.1)),          # CX + its channel
+           ("chan", (2,), amp(2, 0.2)), ("gate", G("U", (2,), U=C.haar_unitary(2, rng))),  # the other qubit
+           ("gate", G("Z", (3,), (0,), (0,))), ("chan", (3,), dep(2, 0.05)),            # controlled phase
+           ("gate", G("U", (2,), (3,), (1,), U=C.haar_unitary(2, rng))),                # controlled dense
+           ("chan", (2,), amp(2, 0.3)), ("chan", (3,), dep(2, 0.2)),
+           ("gate", G("X", (1,), (0,), (1,), a=2)), ("chan", (1,), dep(3, 0.1)),        # qubit-qutrit: span 6
+           ("gate", G("U", (0, 3), U=C.haar_unitary(4, rng))), ("chan", (0,), amp(2, 0.1))]
+    want = Dm.from_state(O.basis_state(dims))
+    for o in ops:
+        if o[0] == "gate":
+            g = o[1]
+            want = Dm.apply_unitary(want, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
+        else:
+            want = Dm.apply_channel(want, dims, o[1], o[2])
+    a = Q.qd_density_init(dims, Q.QD_C128, stream)
+    b = Q.qd_density_init(dims, Q.QD_C128, stream)
+    try:
+        Q.qd_density_apply_ops(a, ops)
+        for o in ops:
+            if o[0] == "gate":
+                Q.apply_circuit_gate_density(b, o[1], dims)
+            else:
+                Q.qd_density_apply_channel(b, o[1], o[2])
+        ga, gb = download_rho(a, dims), download_rho(b, dims)
+        assert np.max(np.abs(ga - want)) <= 1e-12 and np.max(np.abs(gb - want)) <= 1e-12
+        assert abs(np.trace(ga) - 1.0) <= 1e-12
+    finally:
+        Q.qd_state_free(a)
+        Q.qd_state_free(b)
