@@ -237,11 +237,14 @@ def test_operation_sequences_fuse_and_match(stream):
         Q.qd_state_free(b)
 
 
-def test_runs_across_targets_compose_and_match(stream):
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_runs_across_targets_compose_and_match(stream, prec):
     """Consecutive operations whose targets and controls together span qudits of dimension <= 4 (two
     qubits here) are one composed pass: controlled shifts, a controlled phase, a controlled dense
     gate, channels on either qubit and gates on the other, each run embedded on the pair. Against
-    the oracle and against the same operations applied one call at a time."""
+    the oracle and against the same operations applied one call at a time. complex64: each pass
+    rounds a superoperator of side <= 16 and the elements to 24 bits, so at most one pass per
+    operation keeps the max-abs error below 4 x ops x 16 x 2^-24."""
     rng = np.random.default_rng(32)
     dims = (2, 3, 2, 2)
     G = C.Gate
@@ -263,8 +266,9 @@ def test_runs_across_targets_compose_and_match(stream):
             want = Dm.apply_unitary(want, dims, g.targets, g.controls, g.cvals, O.gate_unitary(g, dims))
         else:
             want = Dm.apply_channel(want, dims, o[1], o[2])
-    a = Q.qd_density_init(dims, Q.QD_C128, stream)
-    b = Q.qd_density_init(dims, Q.QD_C128, stream)
+    tol = 1e-12 if prec == Q.QD_C128 else 4.0 * len(ops) * 16 * 2.0 ** -24
+    a = Q.qd_density_init(dims, prec, stream)
+    b = Q.qd_density_init(dims, prec, stream)
     try:
         Q.qd_density_apply_ops(a, ops)
         for o in ops:
@@ -273,8 +277,8 @@ def test_runs_across_targets_compose_and_match(stream):
             else:
                 Q.qd_density_apply_channel(b, o[1], o[2])
         ga, gb = download_rho(a, dims), download_rho(b, dims)
-        assert np.max(np.abs(ga - want)) <= 1e-12 and np.max(np.abs(gb - want)) <= 1e-12
-        assert abs(np.trace(ga) - 1.0) <= 1e-12
+        assert np.max(np.abs(ga - want)) <= tol and np.max(np.abs(gb - want)) <= tol
+        assert abs(np.trace(ga) - 1.0) <= tol
     finally:
         Q.qd_state_free(a)
         Q.qd_state_free(b)
