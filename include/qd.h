@@ -239,6 +239,21 @@ int qd_probabilities(const qd_state* s, double* out, int32_t out_is_device);
  * Synchronises. */
 int qd_norm2(const qd_state* s, double* out);
 
+/* qd_norm2 for callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and the same fixed reduction tree, so
+ * the result is bitwise equal to qd_norm2's, written as one FP64 value to out_dev, a device
+ * pointer the caller owns. Asynchronous on the state's stream (no synchronisation, no host copy).
+ * The reduction partials live in a static 16 KiB device array per GPU (at most 2048 partials,
+ * which covers every register size; a larger grid would return QD_EINVAL) instead of a buffer the
+ * library allocates; the array's device address is looked up once per GPU on the first call.
+ * The call makes no hipMalloc, hipFree or other allocating call. Calls on one GPU share the array:
+ * calls that can overlap in time (on different streams of the same GPU, or from several threads
+ * without ordering) race and must be serialised by the caller. Every workgroup rewrites its own
+ * partial, so no state carries over from one call to the next.
+ * Errors: QD_EINVAL for a null argument, QD_EDEVICE if the array's address cannot be found or
+ * the state's device id is 64 or above, or a launch error. */
+int qd_norm2_noalloc(const qd_state* s, double* out_dev);
+
 /* Precision diagnostics in FP64 against a complex128 reference state of the same register:
  * max_x |psi_x - ref_x|, fidelity loss 1 - |<ref|psi>|^2 (psi unnormalised) and norm drift
  * | ||psi||^2 - 1 |. s may be complex64 or complex128. Any output pointer may be NULL.

@@ -37,7 +37,7 @@ __all__ = [
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
     "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_block_gates", "qd_fused_download_block",
-    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_compare", "qd_compare_ex",
+    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_norm2_noalloc", "qd_compare", "qd_compare_ex",
     "qd_normalize", "qd_sample", "qd_sample_device", "qd_marginals", "qd_support", "qd_ket_string", "kets",
     "qd_circuit_create", "qd_circuit_add", "qd_qasm_parse", "qd_circuit_size", "qd_circuit_dims", "qd_circuit_name",
     "qd_circuit_gate", "qd_circuit_gates", "qd_circuit_moments", "qd_circuit_decompose", "qd_circuit_apply",
@@ -128,6 +128,7 @@ _SIGS = {
     "qd_fused_free": (None, [_P]),
     "qd_probabilities": (C.c_int, [_P, _DP, C.c_int32]),
     "qd_norm2": (C.c_int, [_P, _DP]),
+    "qd_norm2_noalloc": (C.c_int, [_P, _P]),
     "qd_compare": (C.c_int, [_P, _P, _DP, _DP, _DP]),
     "qd_compare_ex": (C.c_int, [_P, _P, _DP]),
     "qd_normalize": (C.c_int, [_P, _DP]),
@@ -474,6 +475,12 @@ def qd_norm2(s: int) -> float:
     v = C.c_double()
     _check(load().qd_norm2(_P(s), C.byref(v)))
     return float(v.value)
+
+
+def qd_norm2_noalloc(s: int, out_dev_ptr: int):
+    """qd_norm2 into one FP64 value at a device address the caller owns; asynchronous, and the
+    library allocates nothing for it."""
+    _check(load().qd_norm2_noalloc(_P(s), _P(out_dev_ptr)))
 
 
 def qd_compare(ref64: int, s: int):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "qd_internal.h"
 #include "qd_stream.h"
@@ -228,6 +229,54 @@ int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st
                        reinterpret_cast<uint4*>(dst) + o, reinterpret_cast<const uint4*>(src) + o, n);
     QD_HIP(hipGetLastError());
   }
+  return QD_OK;
+}
+
+// ------------------------------------------------------------------------------------------ no-allocation norm
+// The partials of the squared-norm reduction of a caller that cannot allocate live in one
+// file-scope device array per GPU, sized for the largest reduction grid. Its device address is
+// looked up once per device (with that device current) and used for every launch; the host-side
+// name of the array is never passed to a kernel.
+constexpr int kStaticRedDoubles = kRedMaxGrid;   // 16 KiB per GPU
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticRedDoubles];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kStaticMaxDevices] = {};
+
+static int static_scratch(int device, double** out) {
+  if (device < 0 || device >= kStaticMaxDevices) return fail(QD_EDEVICE, "device id beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    QD_HIP(hipGetDevice(&cur));
+    if (cur != device) QD_HIP(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) QD_HIP(hipSetDevice(cur));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(QD_EDEVICE, "no device address for the static scratch array");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return QD_OK;
+}
+
+int reduce_norm2_noalloc(const qd_state* s, double* out_dev) {
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned g = red_grid(D);
+  if (g > unsigned(kStaticRedDoubles))
+    return fail(QD_EINVAL, "reduction grid exceeds the static scratch array (2048 partials)");
+  double* part = nullptr;
+  int rc = static_scratch(s->device, &part);
+  if (rc) return rc;
+  // every workgroup writes its own partial, so nothing needs clearing between calls
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_norm_partial<double>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)s->data, D, part);
+  else
+    hipLaunchKernelGGL((k_norm_partial<float>), dim3(g), dim3(kRedBlock), 0, s->stream, (const float*)s->data, D, part);
+  hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(kRedBlock), 0, s->stream, part, g, 1, out_dev);
+  QD_HIP(hipGetLastError());
   return QD_OK;
 }
 

@@ -559,6 +559,11 @@ int qd_norm2(const qd_state* s, double* out) {
   return reduce_norm2(s, out);
 }
 
+int qd_norm2_noalloc(const qd_state* s, double* out_dev) {
+  if (!s || !out_dev) return fail(QD_EINVAL, "null argument");
+  return reduce_norm2_noalloc(s, out_dev);
+}
+
 static int check_compare_args(const qd_state* ref, const qd_state* s) {
   if (!ref || !s) return fail(QD_EINVAL, "null state");
   if (ref->prec != QD_C128) return fail(QD_EDIM, "reference state must be complex128");
