@@ -35,8 +35,6 @@ HBM_PEAK_GBPS = 8000.0
 # VALU instruction per SIMD every 4 cycles; the 157.3 TFLOP/s FP32 figure counts an FMA as two
 # flops and dual-issued packed FP32, neither of which integer digit work uses)
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-ROUTE_NAMES = {0: "k_slices_direct", 1: "k_slices_tiled", 2: "k_diag", 3: "k_dense_generic"}
-CLASS_NAMES = {0: "dense", 1: "monomial", 2: "diagonal"}
 
 
 def log(*a):
@@ -71,21 +69,9 @@ def gate_plan(circ, Q):
     for g in circ.gates:
         U = Q.gate_unitary(g, circ.dims)
         dc = int(np.prod([circ.dims[c] for c in g.controls])) if g.controls else 1
-        route = Q.qd_gate_route(circ.dims, Q.QD_C128, g.targets, g.controls, g.cvals, U)
-        cls = Q.qd_gate_class(U)
         out.append({"t": list(g.targets), "c": list(g.controls), "v": list(g.cvals), "U": U,
-                    "active": D // dc, "key": (route, cls, U.shape[0])})
+                    "active": D // dc, "key": None})
     return out
-
-
-def kernel_name(key):
-    route, cls, dT = key
-    if route == 2:
-        return "k_diag<double>"
-    if route == 3:
-        return "k_dense_generic<double>"
-    op = "DenseOp" if cls == 0 else "MonoOp"
-    return f"{ROUTE_NAMES[route]}<double, {dT}, {op}<double, {dT}>>"
 
 
 def bench_plain(args, Q, torch, circ):
@@ -97,7 +83,7 @@ def bench_plain(args, Q, torch, circ):
     probs = torch.empty(D, dtype=torch.float64, device="cuda")
     zeros = [0] * len(circ.dims)
 
-    def step(ev=None):
+    def step(ev=None, label=False):
         Q.qd_state_set_basis(s, zeros)
         for i, g in enumerate(plan):
             if ev is not None:
@@ -105,10 +91,13 @@ def bench_plain(args, Q, torch, circ):
             Q.qd_apply_gate(s, g["t"], g["c"], g["v"], g["U"])
             if ev is not None:
                 ev[i][1].record()
+            if label:
+                g["key"] = Q.qd_last_kernel()   # the kernel instance the library launched
         Q.qd_probabilities(s, probs.data_ptr())
         return Q.qd_norm2(s)
 
-    for _ in range(args.warmup):
+    step(label=True)          # untimed: the first warm-up step also records each gate's kernel
+    for _ in range(args.warmup - 1):
         step()
     events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in plan]
               for _ in range(args.steps)]
@@ -136,7 +125,7 @@ def bench_plain(args, Q, torch, circ):
     total_bytes = sum(2.0 * 16.0 * g["active"] for g in plan)
     gate_ms = sum(v["ms"] for v in per_key.values()) / args.steps
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernels = {kernel_name(k): {"launches_per_step": v["n"] // args.steps, "avg_us": 1e3 * v["ms"] / v["n"],
+    kernels = {k: {"launches_per_step": v["n"] // args.steps, "avg_us": 1e3 * v["ms"] / v["n"],
                                 "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                for k, v in sorted(per_key.items(), key=lambda kv: -kv[1]["ms"])}
     return {
@@ -145,7 +134,7 @@ def bench_plain(args, Q, torch, circ):
         "gates_per_s": len(plan) * args.steps / (t1 - t0),
         "hbm_GBps_gates": total_bytes / (gate_ms * 1e-3) / 1e9,
         "norm_drift": max(abs(n - 1.0) for n in norms),
-        "roofline": {"bound": "hbm", "kernel": kernel_name(dom_key), "achieved": achieved, "peak": HBM_PEAK_GBPS,
+        "roofline": {"bound": "hbm", "kernel": dom_key, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels": kernels,

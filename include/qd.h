@@ -86,6 +86,13 @@ const char* qd_version(void);
  * failing call on the same thread). */
 const char* qd_last_error(void);
 
+/* Name of the kernel instance that the calling thread's last qd_apply_gate / qd_apply_gate_ex
+ * launched, e.g. "k_slices_direct<double, 2, DenseOp<double, 2>, 1, plain>" (template arguments:
+ * precision, slice size d_T after any control folded into the targets, gate operation, slices per
+ * thread and the control mode plain / pred / edge); "" when that call launched nothing. Static
+ * thread-local storage, for profiling labels; it changes no state. */
+const char* qd_last_kernel(void);
+
 /* Register table (Sec. 2.2: the state has prod dims[i] entries). Host only, no device work.
  * Writes D to *D_out and the n big-endian strides to strides_out[n] (caller-allocated).
  * QD_EINVAL for n outside 1..64 or null pointers, QD_EDIM for a radix outside 2..256,

@@ -32,7 +32,7 @@ __all__ = [
     "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "QD_TUNE_BATCH_SPT_MID", "QD_TUNE_BATCH_SPT_WIDE",
     "qd_batch_apply_layers", "qd_batch_autotune_layers",
     "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "QD_ROUTE_GEMM", "qd_gate_route",
-    "qd_version", "qd_last_error", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
+    "qd_version", "qd_last_error", "qd_last_kernel", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
@@ -100,6 +100,7 @@ _DP = C.POINTER(C.c_double)
 _SIGS = {
     "qd_version": (C.c_char_p, []),
     "qd_last_error": (C.c_char_p, []),
+    "qd_last_kernel": (C.c_char_p, []),
     "qd_register_strides": (C.c_int, [_I32P, C.c_int32, _I64P, _I64P]),
     "qd_gate_matrix": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _DP]),
     "qd_validate_gate": (C.c_int, [_I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP, C.c_uint32]),
@@ -236,6 +237,11 @@ def qd_version() -> str:
 
 def qd_last_error() -> str:
     return load().qd_last_error().decode()
+
+
+def qd_last_kernel() -> str:
+    """Kernel instance of this thread's last gate launch (a profiling label)."""
+    return load().qd_last_kernel().decode()
 
 
 def qd_register_strides(dims: Sequence[int]):

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -126,6 +127,13 @@ __device__ __forceinline__ void mix_store(C* p, int64_t base, const int64_t*, co
 }
 
 // ------------------------------------------------------------------------------------------ direct
+// Controls whose stride is below one 128-byte line leave every line partly active, and controls of
+// larger stride that is not a whole number of lines leave the lines at both ends of every active
+// run partly active. HBM is written in whole lines here (a partial line costs a read-modify-write),
+// so both cases are applied with whole-line writes: amplitudes of inactive slices that share a line
+// with active ones are read and written back unchanged.
+enum { kDirectPlain = 0, kDirectPred = 1, kDirectEdge = 2 };
+
 template <typename R, int DT, typename OP>
 struct DirectArgs {
   R* psi;
@@ -133,30 +141,141 @@ struct DirectArgs {
   int64_t toff[DT];
   int64_t doff[DT];
   OP op;
+  // kDirectPred: the low-stride controls are free digits of sm (singleton groups whose lmul weights
+  // give their local index); a slice is mixed when that index equals vloc, else written unchanged.
+  uint32_t vloc;
+  // kDirectEdge (every target above the lowest control): sm enumerates the active slices, grouped
+  // into blocks of nA = blen consecutive indices (the blen contiguous amplitudes where the lowest
+  // control holds its value, all higher digits fixed, each a slice base). Each block gets W lanes,
+  // LINE times the most lines a block can touch, taking the amplitudes of those lines in order;
+  // lanes outside the block rewrite their amplitudes unchanged (in every target plane whose line
+  // holds amplitudes of the block).
+  uint32_t nA;
+  uint32_t W;
+  Magic32 wm;
+  uint32_t blen;
+  uint32_t nvirt;
+  int64_t D;
 };
 
-template <typename R, int DT, typename OP, int SPT>
+template <typename R> struct LineAmps;   // amplitudes per 128-byte line
+template <> struct LineAmps<double> { static constexpr int value = 8; };
+template <> struct LineAmps<float> { static constexpr int value = 16; };
+template <typename R> constexpr int kLineShift = sizeof(R) == 8 ? 3 : 4;
+
+// Outputs of one slice where every lane stores position y at the same instruction: the mixed
+// values where the slice is active, its inputs otherwise (a monomial U picks, for each output row,
+// the column whose entry lands there: dst is uniform, so the tests are scalar).
+template <typename C, typename R, int DT>
+__device__ __forceinline__ void mix_select(const DenseOp<R, DT>& op, const C (&x)[DT], bool act, C (&out)[DT]) {
+#pragma unroll
+  for (int r = 0; r < DT; ++r) {
+    R re = R(0), im = R(0);
+#pragma unroll
+    for (int c = 0; c < DT; ++c) {
+      const R ur = op.u[2 * (r * DT + c)], ui = op.u[2 * (r * DT + c) + 1];
+      re = fma(ur, x[c].x, re);
+      re = fma(-ui, x[c].y, re);
+      im = fma(ur, x[c].y, im);
+      im = fma(ui, x[c].x, im);
+    }
+    out[r].x = act ? re : x[r].x;
+    out[r].y = act ? im : x[r].y;
+  }
+}
+
+template <typename C, typename R, int DT>
+__device__ __forceinline__ void mix_select(const MonoOp<R, DT>& op, const C (&x)[DT], bool act, C (&out)[DT]) {
+#pragma unroll
+  for (int y = 0; y < DT; ++y) out[y] = x[y];
+#pragma unroll
+  for (int c = 0; c < DT; ++c) {
+    const R pr = op.ph[2 * c], pi = op.ph[2 * c + 1];
+    C v;
+    v.x = fma(pr, x[c].x, -pi * x[c].y);
+    v.y = fma(pr, x[c].y, pi * x[c].x);
+#pragma unroll
+    for (int y = 0; y < DT; ++y)
+      if (op.dst[c] == y) {
+        out[y].x = act ? v.x : out[y].x;
+        out[y].y = act ? v.y : out[y].y;
+      }
+  }
+}
+
+template <typename R, int DT, typename OP, int SPT, int MODE>
 __global__ __launch_bounds__(256) void k_slices_direct(DirectArgs<R, DT, OP> a) {
   using C = typename CxT<R>::T;
   C* __restrict__ psi = reinterpret_cast<C*>(a.psi);
   const uint64_t bs = blockDim.x;
-  const uint64_t first = uint64_t(blockIdx.x) * bs * SPT + threadIdx.x;
-  int64_t base[SPT];
-  C x[SPT][DT];
+  if constexpr (MODE != kDirectPlain) {
+    // one slice or edge position per thread; position y of every lane is loaded and stored by
+    // one instruction, so each instruction writes whole lines wherever its lanes are consecutive
+    int64_t pos;
+    bool act = true;
+    uint32_t valid = (1u << DT) - 1u;
+    if constexpr (MODE == kDirectPred) {
+      const uint64_t i = uint64_t(blockIdx.x) * bs + threadIdx.x;
+      if (i >= a.sm.count) return;
+      uint32_t loc;
+      pos = sm_offset_loc(a.sm, uint32_t(i), &loc);
+      act = loc == a.vloc;
+    } else {
+      // the block's lanes walk its lines in order: lane j takes amplitude L0 + j, L0 the start of
+      // the line holding the block's first amplitude, so every instruction writes whole lines
+      constexpr int LINE = LineAmps<R>::value;
+      const uint32_t vi = uint32_t(blockIdx.x) * uint32_t(bs) + threadIdx.x;
+      if (vi >= a.nvirt) return;
+      const uint32_t b = magic_div(vi, a.wm);
+      const int64_t start = sm_offset(a.sm, b * a.nA);
+      const int64_t end = start + a.blen - 1;
+      pos = (start & ~int64_t(LINE - 1)) + int64_t(vi - b * a.W);
+      if (pos > (end | int64_t(LINE - 1))) return;
+      act = pos >= start && pos <= end;
+      if (!act) {
+        // outside the block: rewritten unchanged where its line (in each target plane) holds
+        // amplitudes of the block
+        valid = 0;
 #pragma unroll
-  for (int s = 0; s < SPT; ++s) {
-    const uint64_t i = first + s * bs;
-    base[s] = i < a.sm.count ? sm_offset(a.sm, uint32_t(i)) : -1;
-  }
+        for (int y = 0; y < DT; ++y) {
+          const int64_t q = pos + a.toff[y];
+          if ((q >> kLineShift<R>) >= ((start + a.toff[y]) >> kLineShift<R>) &&
+              (q >> kLineShift<R>) <= ((end + a.toff[y]) >> kLineShift<R>) && q < a.D)
+            valid |= 1u << y;
+        }
+        if (!valid) return;
+      }
+    }
+    C x[DT], out[DT];
 #pragma unroll
-  for (int s = 0; s < SPT; ++s)
-    if (base[s] >= 0) {
+    for (int y = 0; y < DT; ++y) {
+      x[y].x = R(0);
+      x[y].y = R(0);
+      if (valid & (1u << y)) x[y] = ld_stream(psi + pos + a.toff[y]);
+    }
+    mix_select<C, R, DT>(a.op, x, act, out);
 #pragma unroll
-      for (int y = 0; y < DT; ++y) x[s][y] = ld_stream(psi + base[s] + a.toff[y]);
+    for (int y = 0; y < DT; ++y)
+      if (valid & (1u << y)) st_stream(psi + pos + a.toff[y], out[y]);
+  } else {
+    const uint64_t first = uint64_t(blockIdx.x) * bs * SPT + threadIdx.x;
+    int64_t base[SPT];
+    C x[SPT][DT];
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+      const uint64_t i = first + s * bs;
+      base[s] = i < a.sm.count ? sm_offset(a.sm, uint32_t(i)) : -1;
     }
 #pragma unroll
-  for (int s = 0; s < SPT; ++s)
-    if (base[s] >= 0) mix_store<true, C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
+    for (int s = 0; s < SPT; ++s)
+      if (base[s] >= 0) {
+#pragma unroll
+        for (int y = 0; y < DT; ++y) x[s][y] = ld_stream(psi + base[s] + a.toff[y]);
+      }
+#pragma unroll
+    for (int s = 0; s < SPT; ++s)
+      if (base[s] >= 0) mix_store<true, C, R, DT>(psi, base[s], a.toff, a.doff, a.op, x[s]);
+  }
 }
 
 // Dense gates of d_T = 12 or 16 whose targets all have strides >= run_min: one slice per thread as
@@ -590,6 +709,37 @@ __global__ __launch_bounds__(256) void k_dense_gemm(R* psi_raw, const unsigned c
 }
 
 // ------------------------------------------------------------------------------------------ launch helpers
+// Name of the kernel instance the calling thread's last gate launch used (qd_last_kernel).
+static thread_local const char* g_last_kernel = "";
+
+template <typename R> constexpr const char* real_name() { return sizeof(R) == 8 ? "double" : "float"; }
+template <typename OP> struct OpName;
+template <typename R, int DT> struct OpName<DenseOp<R, DT>> { static constexpr const char* value = "DenseOp"; };
+template <typename R, int DT> struct OpName<MonoOp<R, DT>> { static constexpr const char* value = "MonoOp"; };
+
+// "<kernel><R, DT[, Op<R, DT>][, SPT, mode]>", formatted once per instance
+enum { kKnDirect, kKnTiled, kKnDiag, kKnGeneric, kKnGemm, kKnLu };
+template <int KIND, typename R, int DT = 0, typename OP = void, int SPT = 0, int MODE = 0>
+static const char* label() {
+  static thread_local char buf[160] = {0};
+  if (!buf[0]) {
+    static const char* kn[] = {"k_slices_direct", "k_slices_tiled", "k_diag", "k_dense_generic", "k_dense_gemm",
+                               "k_slices_direct_lu"};
+    static const char* modes[] = {"plain", "pred", "edge"};
+    const char* rn = real_name<R>();
+    if constexpr (KIND == kKnDirect)
+      std::snprintf(buf, sizeof(buf), "%s<%s, %d, %s<%s, %d>, %d, %s>", kn[KIND], rn, DT, OpName<OP>::value, rn, DT, SPT,
+                    modes[MODE]);
+    else if constexpr (KIND == kKnTiled)
+      std::snprintf(buf, sizeof(buf), "%s<%s, %d, %s<%s, %d>>", kn[KIND], rn, DT, OpName<OP>::value, rn, DT);
+    else if constexpr (KIND == kKnLu)
+      std::snprintf(buf, sizeof(buf), "%s<%s, %d>", kn[KIND], rn, DT);
+    else
+      std::snprintf(buf, sizeof(buf), "%s<%s>", kn[KIND], rn);
+  }
+  return buf;
+}
+
 static inline unsigned grid_for(uint64_t items, uint64_t per_block) {
   const uint64_t g = (items + per_block - 1) / per_block;
   return unsigned(std::max<uint64_t>(1, g));
@@ -803,6 +953,7 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
       // workgroups walk the tiles; at most 2^22 of them keep the grid inside 32-bit work-item counts
       const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(1) << 22));
       hipLaunchKernelGGL((k_slices_tiled<R, DT, OP>), dim3(grid), dim3(ent.block), lds, s->stream, a);
+      g_last_kernel = label<kKnTiled, R, DT, OP>();
       return check_launch("k_slices_tiled");
     }
   }
@@ -812,22 +963,76 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   std::memset(&a, 0, sizeof(a));
   a.psi = reinterpret_cast<R*>(s->data);
   a.op = op;
+  const int64_t line = LineAmps<R>::value;
+  // controls below one line are free digits of the slice map, tested per slice (kDirectPred)
+  uint32_t lmul[QD_MAX_QUDITS] = {};
+  int nlow = 0, c0 = -1;
+  {
+    uint32_t w = 1;
+    for (int j = p.m - 1; j >= 0; --j) {
+      const int c = p.controls[j];
+      if (r.strides[c] < line) {
+        role[c] = 2;
+        lmul[c] = w;
+        a.vloc += uint32_t(p.cvals[j]) * w;
+        w *= uint32_t(r.dims[c]);
+        ++nlow;
+      } else if (c0 < 0 || r.strides[c] < r.strides[c0]) {
+        c0 = c;
+      }
+    }
+  }
   int64_t base = 0;
-  for (int j = 0; j < p.m; ++j) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
-  int rc = fill_slicemap(make_groups(r, role, nullptr, 0, r.n), base, &a.sm);
+  for (int j = 0; j < p.m; ++j)
+    if (role[p.controls[j]] == 1) base += int64_t(p.cvals[j]) * r.strides[p.controls[j]];
+  int rc = fill_slicemap(make_groups(r, role, nlow ? lmul : nullptr, 0, r.n), base, &a.sm);
   if (rc) return rc;
   target_offsets(r, p, a.toff);
   fill_doff<DT>(p, a.toff, a.doff);
   if (a.sm.count == 0) return QD_OK;
   const int bs = ent.block;
+  if (nlow) {
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1, kDirectPred>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0,
+                       s->stream, a);
+    g_last_kernel = label<kKnDirect, R, DT, OP, 1, kDirectPred>();
+    return check_launch("k_slices_direct");
+  }
+  // the lowest control's active runs end inside lines: edge lanes rewrite the rest of those lines
+  bool above = c0 >= 0;
+  for (int j = 0; j < p.k && above; ++j) above = r.strides[p.targets[j]] > r.strides[c0];
+  if (above && r.strides[c0] % line != 0) {
+    const int64_t sc = r.strides[c0];
+    uint64_t nA = 1;   // every qudit below the control is free (the targets are above it)
+    for (int i = r.n - 1; i >= 0 && r.strides[i] < sc; --i) nA *= uint64_t(r.dims[i]);
+    const uint64_t nblk = a.sm.count / nA;
+    const uint64_t W = (uint64_t(sc) + 2 * uint64_t(line) - 2) / uint64_t(line) * uint64_t(line);   // lines a block can touch
+    if (nblk * nA == a.sm.count && nblk * W <= 0xFFFFFFFFull) {
+      a.nA = uint32_t(nA);
+      a.W = uint32_t(W);
+      a.wm = make_magic32(uint32_t(W));
+      a.blen = uint32_t(sc);
+      a.nvirt = uint32_t(nblk * W);
+      a.D = r.D;
+      hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1, kDirectEdge>), dim3(grid_for(a.nvirt, uint64_t(bs))), dim3(bs), 0,
+                         s->stream, a);
+      g_last_kernel = label<kKnDirect, R, DT, OP, 1, kDirectEdge>();
+      return check_launch("k_slices_direct");
+    }
+  }
   // Several slices per thread only up to d_T = 4: beyond, two slices' operands and the gate's
   // kernel arguments overflow the scalar registers and the spilled values are read back per FMA.
   if (ent.spt >= 4 && DT <= 4) {
-    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 4>), dim3(grid_for(a.sm.count, uint64_t(bs) * 4)), dim3(bs), 0, s->stream, a);
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 4, kDirectPlain>), dim3(grid_for(a.sm.count, uint64_t(bs) * 4)), dim3(bs),
+                       0, s->stream, a);
+    g_last_kernel = label<kKnDirect, R, DT, OP, 4, kDirectPlain>();
   } else if (ent.spt >= 2 && DT <= 4) {
-    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 2, kDirectPlain>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs),
+                       0, s->stream, a);
+    g_last_kernel = label<kKnDirect, R, DT, OP, 2, kDirectPlain>();
   } else {
-    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0, s->stream, a);
+    hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1, kDirectPlain>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0,
+                       s->stream, a);
+    g_last_kernel = label<kKnDirect, R, DT, OP, 1, kDirectPlain>();
   }
   return check_launch("k_slices_direct");
 }
@@ -869,6 +1074,7 @@ static int launch_diag(qd_state* s, const GatePlan& p) {
   if (a.sm.count == 0) return QD_OK;
   const int bs = tune().diag_block;
   hipLaunchKernelGGL((k_diag<R, 2>), dim3(grid_for(a.sm.count, uint64_t(bs) * 2)), dim3(bs), 0, s->stream, a);
+  g_last_kernel = label<kKnDiag, R>();
   return check_launch("k_diag");
 }
 
@@ -898,6 +1104,7 @@ static int launch_generic(qd_state* s, const GatePlan& p) {
   const size_t lds = size_t(h->nsw) * p.dT * sizeof(R) * 2;
   hipLaunchKernelGGL((k_dense_generic<R>), dim3(grid), dim3(256), lds, s->stream, reinterpret_cast<R*>(s->data),
                      static_cast<const unsigned char*>(dev));
+  g_last_kernel = label<kKnGeneric, R>();
   return check_launch("k_dense_generic");
 }
 
@@ -925,6 +1132,7 @@ static int launch_direct_lu(qd_state* s, const GatePlan& p) {
   if (rc) return rc;
   hipLaunchKernelGGL((k_slices_direct_lu<R, DT>), dim3(grid_for(h->sm.count, 256)), dim3(256), 0, s->stream,
                      reinterpret_cast<R*>(s->data), static_cast<const unsigned char*>(dev));
+  g_last_kernel = label<kKnLu, R, DT>();
   return check_launch("k_slices_direct_lu");
 }
 
@@ -979,6 +1187,7 @@ static int launch_gemm(qd_state* s, const GatePlan& p) {
   const unsigned grid = unsigned(std::min<uint64_t>(ntiles, uint64_t(cus) * per_cu));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s->stream, reinterpret_cast<R*>(s->data),
                      static_cast<const unsigned char*>(dev));
+  g_last_kernel = label<kKnGemm, R>();
   return check_launch("k_dense_gemm");
 }
 
@@ -988,7 +1197,11 @@ static int launch_gate_t(qd_state* s, const GatePlan& p) {
   if (route == QD_ROUTE_GENERIC) return launch_generic<R>(s, p);
   if (route == QD_ROUTE_GEMM) return launch_gemm<R>(s, p);
   if (route == QD_ROUTE_DIAG) return launch_diag<R>(s, p);
-  if (p.cls == QD_CLASS_MONOMIAL) {
+  // On the slice-per-thread kernel a monomial U up to d_T = 9 runs as a dense one: each thread then
+  // issues all its loads before its stores, which measured faster than storing every output as soon
+  // as its one input arrives (a ququart shift 607 -> 588 us on a 1.7 GB state; with a control below
+  // one line 720 -> 575 us), and the zero entries add exact zeros.
+  if (p.cls == QD_CLASS_MONOMIAL && !(route == QD_ROUTE_DIRECT && p.dT <= kMaxInlineDense)) {
     switch (p.dT) {
       case 2: return launch_mono_t<R, 2>(s, p);
       case 3: return launch_mono_t<R, 3>(s, p);
@@ -1019,7 +1232,10 @@ static int launch_gate_t(qd_state* s, const GatePlan& p) {
 }
 
 int launch_gate(qd_state* s, const GatePlan& p) {
+  g_last_kernel = "";
   return s->prec == QD_C128 ? launch_gate_t<double>(s, p) : launch_gate_t<float>(s, p);
 }
+
+const char* last_kernel() { return g_last_kernel; }
 
 }  // namespace qd

@@ -75,6 +75,8 @@ const char* qd_version(void) { return "libqd 1.0 (gfx950)"; }
 
 const char* qd_last_error(void) { return g_last_error.c_str(); }
 
+const char* qd_last_kernel(void) { return last_kernel(); }
+
 int qd_register_strides(const int32_t* dims, int32_t n, int64_t* D_out, int64_t* strides_out) {
   if (!D_out || !strides_out) return fail(QD_EINVAL, "null output");
   Register r;
@@ -230,8 +232,9 @@ void make_plan(const Register& r, const int32_t* targets, int32_t k, const int32
 // A control whose stride is below one 128-byte line of amplitudes leaves every line partly
 // active: a pass over the matching slices still moves whole lines, and with its partial writes
 // such gates measured slower than a full pass (about 1 ms against 0.57 ms on a 1.7 GB state).
-// Those controls become targets of an embedded gate (U where they hold their values, the identity
-// elsewhere, exactly), which one coalesced pass applies, provided it keeps a fast kernel.
+// Where no kernel writes those lines whole for the gate as given (diagonal gates, dense d_T above
+// 9), such controls become targets of an embedded gate (U where they hold their values, the
+// identity elsewhere, exactly), which one coalesced pass applies, provided it keeps a fast kernel.
 void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, const int32_t* controls,
                const int32_t* cvals, int32_t m, const double* U, GatePlan* p) {
   make_plan(r, targets, k, controls, cvals, m, U, p);
@@ -239,6 +242,12 @@ void plan_gate(const Register& r, int prec, const int32_t* targets, int32_t k, c
   std::vector<int> low, keep;
   for (int j = 0; j < m; ++j) (r.strides[controls[j]] < line ? low : keep).push_back(j);
   if (low.empty()) return;
+  // The slice-per-thread kernel takes such controls as free digits tested per slice, and the LDS
+  // tile kernel stages every value of a control inside its suffix and mixes the matching slices
+  // only: both write whole lines while mixing d_T amplitudes per slice, so no folding there.
+  const int route0 = route_gate(r, prec, *p);
+  if (route0 == QD_ROUTE_TILED) return;
+  if (route0 == QD_ROUTE_DIRECT && (p->cls == QD_CLASS_MONOMIAL || p->dT <= kMaxInlineDense)) return;
   int dC = 1;
   for (int j : low) dC *= r.dims[controls[j]];
   const int dT = p->dT, dG = dT * dC;

@@ -516,3 +516,58 @@ def test_tiled_kernel_walks_tiles_beyond_the_grid_cap(stream, prec):
     finally:
         for s in states:
             Q.qd_state_free(s)
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_direct_controls_whole_lines(stream, prec):
+    """Controlled gates on the slice-per-thread kernel where the control's active runs do not
+    cover whole 128-byte lines: controls of stride below one line (tested per slice, every slice
+    written), and a lowest control whose stride is not a whole number of lines (edge lanes rewrite
+    the rest of the partly active lines): targets above and below the control, two controls, the
+    last line of a register whose size is no multiple of a line, dense and monomial U, each
+    against the oracle."""
+    line = 8 if prec == Q.QD_C128 else 16
+    regs = {
+        # strides 4320, 2160, 540, 180, 90, 18, 6, 3, 1 (D = 12960)
+        (3, 2, 4, 3, 2, 5, 3, 2, 3): [
+            ((0,), (8,), (2,)), ((2,), (7,), (1,)), ((3,), (6, 8), (1, 0)), ((1,), (6, 4), (2, 1)),
+            ((5,), (7,), (1,)), ((0,), (5,), (2,)), ((2,), (4,), (1,)), ((5,), (3,), (0,)),
+            ((1, 4), (3,), (1,)), ((0,), (5, 3), (1, 2)), ((0,), (2,), (3,)), ((0,), (1,), (1,)),
+            ((4, 1), (5,), (4,)),
+        ],
+        # strides 135, 45, 9, 3, 1 (D = 405: the last line is partial)
+        (3, 3, 5, 3, 3): [((0,), (2,), (4,)), ((1,), (2,), (0,)), ((0,), (1,), (2,)), ((0, 1), (2,), (3,))],
+    }
+    rng = C.seeded_rng(97)
+    seen = set()
+    for dims, cases in regs.items():
+        D = O.register_size(dims)
+        st = O.strides(dims)
+        psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+        psi0 /= np.linalg.norm(psi0)
+        for t, c, v in cases:
+            dT = int(np.prod([dims[q] for q in t]))
+            low = min(st[q] for q in c)
+            kind = "pred" if low < line else ("edge" if low % line else "aligned")
+            seen.add(kind)
+            mono = np.eye(dT)[np.roll(np.arange(dT), 1)] * np.exp(1j * rng.random(dT))
+            for U in (C.haar_unitary(dT, rng), mono):
+                assert Q.qd_gate_route(dims, prec, t, c, v, U) == Q.QD_ROUTE_DIRECT, (dims, t, c)
+                s = Q.qd_state_init(dims, prec, stream)
+                try:
+                    Q.qd_state_upload(s, psi0)
+                    Q.qd_apply_gate(s, t, c, v, U)
+                    out = Q.qd_state_download(s)
+                finally:
+                    Q.qd_state_free(s)
+                ref = O.apply_gate(psi0, dims, t, c, v, U)
+                tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, dT)
+                assert max_abs(out, ref) <= tol, (dims, t, c, kind, prec)
+                # amplitudes outside the active slices are bit-identical (rewritten unchanged)
+                act = np.ones(D, bool)
+                idx = np.arange(D)
+                for q, val in zip(c, v):
+                    act &= (idx // st[q]) % dims[q] == val
+                x0 = psi0.astype(out.dtype)
+                assert np.array_equal(out[~act], x0[~act]), (dims, t, c, kind)
+    assert seen == {"pred", "edge", "aligned"}
