@@ -22,13 +22,11 @@ Readings (each shared with the library and stated in its header):
   * arithmetic: a complex product u*x is formed as (ur*xr - ui*xi, ur*xi + ui*xr), each real
     operation rounded on its own (no fused multiply-add), and a dense output is the sum over
     columns j = 0, 1, .., d_T - 1 in that order starting from +0.0. This fixes every bit of the
-    result, and so every drop decision;
-  * list order (a convention of the library, not of the paper): a monomial gate keeps every entry
-    at its position; a dense gate keeps non-matching entries in their order and writes each slice's
-    non-zero outputs, in increasing local row, where the slice's first entry stood.
+    result, and so every drop decision.
 
-The state is a pair of arrays: flat indices (int64, distinct) and amplitudes (complex128), in list
-order.
+The state is a pair of arrays: flat indices (int64, distinct) and amplitudes (complex128), in
+increasing index, the order of a compressed sparse column (Sec. 3.3). A library may keep its list
+in another order; the entries themselves are unique.
 """
 from __future__ import annotations
 
@@ -128,17 +126,13 @@ def apply_gate(dims: Sequence[int], idx: np.ndarray, amp: np.ndarray, targets, c
         re, im = _cmul(u.real[scale], u.imag[scale], amp.real[ms], amp.imag[ms])
         out_amp.real[ms] = re                          # the parts are stored as computed
         out_amp.imag[ms] = im
-        return out_idx, out_amp
+        return _ascending(out_idx, out_amp)
 
-    # dense gate: slices in order of their first entry
+    # dense gate: one slice per distinct base among the matching entries
     m = np.flatnonzero(match)
-    keys = base[m]
-    uniq, first, inv = np.unique(keys, return_index=True, return_inverse=True)
-    order = np.argsort(first, kind="stable")          # slice ranks by first appearance
-    rank = np.empty_like(order)
-    rank[order] = np.arange(order.size)
-    sid = rank[inv.reshape(-1)]
-    ns = uniq.size
+    slice_key, sid = np.unique(base[m], return_inverse=True)
+    sid = sid.reshape(-1)
+    ns = slice_key.size
     Xr = np.zeros((ns, dT))
     Xi = np.zeros((ns, dT))
     Xr[sid, loc[m]] = amp.real[m]
@@ -154,22 +148,20 @@ def apply_gate(dims: Sequence[int], idx: np.ndarray, amp: np.ndarray, targets, c
             acc_i = acc_i + pi
         Yr[:, i] = acc_r
         Yi[:, i] = acc_i
-    slice_key = uniq[order]                           # key of the slice of rank s
-    slice_pos = m[first[order]]                       # list position of its first entry
-    keep = (Yr != 0) | (Yi != 0)
-    s_of, i_of = np.nonzero(keep)                     # row-major: slice rank, then row
+    keep = (Yr != 0) | (Yi != 0)                      # exact zeros are not stored
+    s_of, i_of = np.nonzero(keep)
     new_idx = slice_key[s_of] + offset(i_of)
     new_amp = np.empty(s_of.size, dtype=np.complex128)
     new_amp.real = Yr[s_of, i_of]
     new_amp.imag = Yi[s_of, i_of]
-    # merge with the non-matching entries by list position (slice outputs sit at their first entry)
-    p = np.flatnonzero(~match)
-    pos = np.concatenate([p, slice_pos[s_of]])
-    sub = np.concatenate([np.zeros(p.size, dtype=np.int64), i_of.astype(np.int64)])
-    order2 = np.lexsort((sub, pos))
-    all_idx = np.concatenate([idx[p], new_idx])[order2]
-    all_amp = np.concatenate([amp[p], new_amp])[order2]
-    return all_idx, all_amp
+    p = np.flatnonzero(~match)                        # entries the gate leaves as they are
+    return _ascending(np.concatenate([idx[p], new_idx]), np.concatenate([amp[p], new_amp]))
+
+
+def _ascending(idx: np.ndarray, amp: np.ndarray):
+    """The entries in increasing index (indices are distinct)."""
+    order = np.argsort(idx, kind="stable")
+    return idx[order], amp[order]
 
 
 def run_circuit(circuit, idx=None, amp=None):
@@ -180,6 +172,7 @@ def run_circuit(circuit, idx=None, amp=None):
             idx, amp = from_dense(initial_state(circuit))
         else:
             idx, amp = basis(dims, getattr(circuit, "init_basis", None))
+    idx, amp = _ascending(np.asarray(idx, dtype=np.int64), np.asarray(amp, dtype=np.complex128))
     for g in circuit.gates:
         idx, amp = apply_gate(dims, idx, amp, g.targets, g.controls, g.cvals, gate_unitary(g, dims))
     return idx, amp

@@ -1,12 +1,15 @@
 """GPU sparse state (qd_sparse_*) against the sparse oracle.
 
-Entry lists are compared element by element in list order: indices exactly, amplitudes exactly
-(both sides form every product and every sum in the same order with each real operation rounded on
-its own). The two sides build their named-gate matrices separately and those can differ only in
-the sign of a zero entry, so amplitudes are compared part by part with ==, under which +0.0 and -0.0
-are equal. Full-size Toffoli networks (2^24 entries on a 2^32 x 3^8 register, far beyond any dense
-state) are checked against the oracle on sampled basis states and by properties that hold at any
-size.
+The entries of a state are unique, their order in the library's list is not (the paper's compressed
+column keeps indices sorted, the library keeps its own deterministic order): the GPU list is sorted
+by index and compared entry by entry with the oracle's, which is in increasing index. Indices must
+match exactly and amplitudes exactly (both sides form every product and every sum in the same order
+with each real operation rounded on its own). The two sides build their named-gate matrices
+separately and those can differ only in the sign of a zero entry, so amplitudes are compared part
+by part with ==, under which +0.0 and -0.0 are equal. The library's own list order is checked
+separately for run-to-run determinism. Full-size Toffoli networks (2^24 entries on a 2^32 x 3^8
+register, far beyond any dense state) are checked against the oracle on sampled basis states and by
+properties that hold at any size.
 """
 import math
 
@@ -29,11 +32,26 @@ def stream():
     return torch_stream()
 
 
+def by_index(entries):
+    """The entries of a list in increasing index."""
+    idx, amp = entries
+    order = np.argsort(idx, kind="stable")
+    return idx[order], amp[order]
+
+
 def same_list(got, want):
-    gi, ga = got
+    """Same entries (index and amplitude bits), whatever the library's list order."""
+    gi, ga = by_index(got)
     wi, wa = want
+    assert np.all(np.diff(wi) > 0)
     assert gi.tolist() == wi.tolist()
     assert np.all(ga.real == wa.real) and np.all(ga.imag == wa.imag)
+
+
+def identical_lists(a, b):
+    """The same list, order included (run-to-run determinism of the library)."""
+    assert a[0].tolist() == b[0].tolist()
+    assert np.all(a[1].real == b[1].real) and np.all(a[1].imag == b[1].imag)
 
 
 def nonzero_entries(psi):
@@ -80,7 +98,7 @@ def test_three_target_gates_from_a_superposition(stream):
 def test_generalized_ghz(stream, d, n):
     dims = (d,) * n
     gates = [C.Gate("F", (0,))] + [C.Gate("X", (k,), (0,), (v,), a=v) for k in range(1, n) for v in range(1, d)]
-    idx, amp = run_sparse(dims, gates, stream)
+    idx, amp = by_index(run_sparse(dims, gates, stream))
     step = sum(d ** (n - 1 - q) for q in range(n))
     assert idx.tolist() == [j * step for j in range(d)]
     assert np.all(amp == complex(1.0 / math.sqrt(d), 0.0))
@@ -153,7 +171,7 @@ def test_invalid_arguments_leave_the_state_unchanged(stream):
             Q.qd_sparse_apply_gate(sp, (0,), (), (), 2 * O.x_gate(2))        # not unitary
         with pytest.raises(Q.QDError):
             Q.qd_sparse_set_basis(sp, (0, 3))
-        same_list(Q.qd_sparse_download(sp), before)
+        identical_lists(Q.qd_sparse_download(sp), before)
     finally:
         Q.qd_sparse_free(sp)
 
@@ -402,3 +420,22 @@ def test_long_runs_and_gates_a_run_cannot_hold(stream):
         Q.qd_sparse_free(sp)
     assert len(want[0]) == 64
     same_list(got, want)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_list_order_is_deterministic(stream, seed):
+    """The library's list order (its own convention) is the same on every run of a circuit, gate by
+    gate and as fused runs, on random circuits with dense and monomial gates."""
+    rng = C.seeded_rng(400 + seed)
+    dims = (2, 3, 2, 4, 3, 2, 2)
+    circ = C.random_circuit(dims, 50, rng, max_targets=2, max_controls=2)
+    runs = [run_sparse(dims, circ.gates, stream) for _ in range(2)]
+    identical_lists(runs[0], runs[1])
+    for _ in range(2):
+        sp = Q.qd_sparse_init(dims, 0, stream)
+        try:
+            Q.qd_sparse_apply_gates(sp, circ.gates)
+            identical_lists(Q.qd_sparse_download(sp), runs[0])
+        finally:
+            Q.qd_sparse_free(sp)
+    same_list(runs[0], S.run_circuit(circ))

@@ -7,7 +7,7 @@
   dense state; the generalized GHZ state has d entries of exactly 1/sqrt(d); Hadamards on k qubits
   of a 40-qubit register give 2^k entries of equal magnitude; a Hadamard applied twice returns to
   one entry (the cancelled output is exactly zero and is dropped).
-* The list-order rule on a hand-derived example.
+* Entries come in increasing index (the compressed column's order), on a hand-derived example.
 """
 import itertools
 import math
@@ -22,7 +22,7 @@ from oracle import sparse as S
 
 def _check_valid(idx, amp):
     assert idx.dtype == np.int64 and amp.dtype == np.complex128
-    assert len(np.unique(idx)) == len(idx), "indices must be distinct"
+    assert np.all(np.diff(idx) > 0), "indices distinct and increasing"
     assert np.all((amp.real != 0) | (amp.imag != 0)), "no stored zero"
 
 
@@ -98,10 +98,11 @@ def test_permutations_move_a_superposition_without_touching_amplitudes():
     perm = C.permutation_circuit(dims, 200, rng)
     idx0, amp0 = S.run_circuit(C.Circuit(dims, had))
     idx, amp = S.run_circuit(C.Circuit(dims, perm.gates), idx0, amp0)
-    assert np.array_equal(amp, amp0)                 # same positions, same bits
-    for x0, x in zip(idx0.tolist(), idx.tolist()):
-        dg0 = O.digits_of(x0, dims)
-        assert x == _flat(dims, _digit_walk(dims, perm.gates, dg0))
+    _check_valid(idx, amp)
+    # each entry lands where the digit walk sends its index, with the same bits
+    moved = {_flat(dims, _digit_walk(dims, perm.gates, O.digits_of(x0, dims))): a for x0, a in zip(idx0.tolist(), amp0)}
+    assert sorted(moved) == idx.tolist()
+    assert all(moved[x] == a for x, a in zip(idx.tolist(), amp))
 
 
 @pytest.mark.parametrize("d,n", [(2, 5), (3, 4), (4, 3), (5, 3)])
@@ -133,23 +134,25 @@ def test_cancelled_output_is_dropped():
     assert idx.tolist() == [0] and abs(amp[0] - 1.0) < 1e-15
 
 
-def test_list_order_rule():
-    # dims (2, 3): flat index 3*q0 + q1. List [(4, a), (0, b), (3, b)]; F_2 on qudit 0 forms the
-    # slice q1 = 1 (first at position 0: inputs x = (0, a)) and the slice q1 = 0 (first at position
-    # 1: x = (b, b), whose row-1 output b/sqrt2 - b/sqrt2 is exactly zero). Expected list: the
-    # q1 = 1 slice's rows 0 and 1 (indices 1, 4), then the q1 = 0 slice's row 0 (index 0).
+def test_entries_in_increasing_index():
+    # dims (2, 3): flat index 3*q0 + q1. Entries (4, a), (0, b), (3, b) given out of order; F_2 on
+    # qudit 0 forms the slice q1 = 1 (inputs x = (0, a): outputs at 1 and 4) and the slice q1 = 0
+    # (x = (b, b), whose row-1 output b/sqrt2 - b/sqrt2 is exactly zero and dropped: output at 0).
     dims = (2, 3)
     a, b = 0.6 - 0.2j, 0.5 + 0.3j
     idx0 = np.array([4, 0, 3], dtype=np.int64)
     amp0 = np.array([a, b, b])
     idx, amp = S.apply_gate(dims, idx0, amp0, (0,), (), (), O.f_gate(2))
-    assert idx.tolist() == [1, 4, 0]
+    assert idx.tolist() == [0, 1, 4]
     dense = O.apply_gate(S.to_dense(dims, idx0, amp0), dims, (0,), (), (), O.f_gate(2))
     assert np.max(np.abs(amp - dense[idx])) < 1e-15
-    # F_3 on qudit 1 controlled by q0 = 1: entries 4 and 3 form one slice (first at position 0),
-    # whose three outputs 3, 4, 5 come first; the non-matching entry 0 keeps its place after them
-    idx2, _ = S.apply_gate(dims, idx0, amp0, (1,), (0,), (1,), O.f_gate(3))
-    assert idx2.tolist() == [3, 4, 5, 0]
+    # F_3 on qudit 1 controlled by q0 = 1: entries 4 and 3 form one slice with outputs 3, 4, 5;
+    # the non-matching entry 0 is kept
+    idx2, amp2 = S.apply_gate(dims, idx0, amp0, (1,), (0,), (1,), O.f_gate(3))
+    assert idx2.tolist() == [0, 3, 4, 5] and amp2[0] == b
+    # a monomial gate that sends the largest index to the smallest: X_{+1} on qudit 0
+    idx3, amp3 = S.apply_gate(dims, np.array([4, 0]), np.array([a, b]), (0,), (), (), O.x_gate(2, 1))
+    assert idx3.tolist() == [1, 3] and amp3.tolist() == [a, b]
 
 
 def test_gate_classes():
