@@ -57,6 +57,7 @@ enum {
 
 enum { QD_C128 = 0, QD_C64 = 1 };                                   /* state precision */
 enum { QD_MODE_FP64_PLAIN = 0, QD_MODE_FP32_MFMA = 1, QD_MODE_BF16X3_MFMA = 2 };
+enum { QD_FUSED_RENORMALIZE = 0x100 };   /* qd_apply_fused flag, OR'd into the mode */
 enum { QD_FLAG_SKIP_UNITARY_CHECK = 1 };
 enum { QD_GATE_X = 0, QD_GATE_Z = 1, QD_GATE_F = 2, QD_GATE_I = 3 };   /* named gates, Sec. 2.1 */
 enum { QD_CLASS_DENSE = 0, QD_CLASS_MONOMIAL = 1, QD_CLASS_DIAGONAL = 2 };
@@ -230,7 +231,14 @@ int qd_fused_download_block(const qd_fused* f, int32_t b, double* out);
  *   QD_MODE_FP32_MFMA: complex64 state, FP32 blocks on FP32 matrix cores, FP32 accumulation;
  *   QD_MODE_BF16X3_MFMA: complex64 state, split-BF16 products a_hi b_hi + a_hi b_lo + a_lo b_hi
  *   on BF16 matrix cores with FP32 accumulation.
- * QD_EDIM if the register or precision does not match the mode. Asynchronous. */
+ * mode may carry QD_FUSED_RENORMALIZE: after the last block the state is brought back to
+ * sum |alpha|^2 = 1 (Eq. (1)) on the GPU, an FP64 reduction of ||psi||^2 (the tree of qd_norm2)
+ * followed by a scaling by 1/sqrt(||psi||^2) computed in FP64 on the device, with no host wait (a
+ * norm of zero or not finite leaves the state as it is). The unit norm of every circuit's state is
+ * exact in exact arithmetic, so this removes only the drift that rounding of the blocks (held to
+ * BF16 pairs in QD_MODE_BF16X3_MFMA) accumulates.
+ * QD_EDIM if the register or precision does not match the mode, QD_EINVAL for another flag.
+ * Asynchronous. */
 int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode);
 
 void qd_fused_free(qd_fused* f);

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "QDError", "lib_path", "load",
     "QD_OK", "QD_EINVAL", "QD_EDIM", "QD_ENOTUNITARY", "QD_ENOMEM", "QD_EOVERFLOW", "QD_EDEVICE",
-    "QD_C128", "QD_C64", "QD_MODE_FP64_PLAIN", "QD_MODE_FP32_MFMA", "QD_MODE_BF16X3_MFMA",
+    "QD_C128", "QD_C64", "QD_MODE_FP64_PLAIN", "QD_MODE_FP32_MFMA", "QD_MODE_BF16X3_MFMA", "QD_FUSED_RENORMALIZE",
     "QD_FLAG_SKIP_UNITARY_CHECK", "QD_GATE_X", "QD_GATE_Z", "QD_GATE_F", "QD_GATE_I",
     "QD_CLASS_DENSE", "QD_CLASS_MONOMIAL", "QD_CLASS_DIAGONAL",
     "QD_CHANNEL_DEPOLARIZING", "QD_CHANNEL_DEPHASING", "QD_CHANNEL_AMPLITUDE_DAMPING",
@@ -56,6 +56,7 @@ __all__ = [
 QD_OK, QD_EINVAL, QD_EDIM, QD_ENOTUNITARY, QD_ENOMEM, QD_EOVERFLOW, QD_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 QD_C128, QD_C64 = 0, 1
 QD_MODE_FP64_PLAIN, QD_MODE_FP32_MFMA, QD_MODE_BF16X3_MFMA = 0, 1, 2
+QD_FUSED_RENORMALIZE = 0x100
 QD_FLAG_SKIP_UNITARY_CHECK = 1
 QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
 QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2

@@ -290,8 +290,11 @@ int qd_fused_download_block(const qd_fused* f, int32_t b, double* out) {
   return QD_OK;
 }
 
-int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode) {
+int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode_flags) {
   if (!s || !f) return fail(QD_EINVAL, "null argument");
+  if (mode_flags & ~int32_t(0xFF | QD_FUSED_RENORMALIZE)) return fail(QD_EINVAL, "unknown mode flag");
+  const int32_t mode = mode_flags & 0xFF;
+  const bool renorm = (mode_flags & QD_FUSED_RENORMALIZE) != 0;
   if (s->reg.n != f->reg.n) return fail(QD_EDIM, "register differs from the fused circuit's");
   for (int i = 0; i < s->reg.n; ++i)
     if (s->reg.dims[i] != f->reg.dims[i]) return fail(QD_EDIM, "register differs from the fused circuit's");
@@ -303,7 +306,7 @@ int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode) {
       int rc = launch_gate(s, p);
       if (rc) return rc;
     }
-    return QD_OK;
+    return renorm ? normalize_on_device(s) : QD_OK;
   }
   if (mode != QD_MODE_FP32_MFMA && mode != QD_MODE_BF16X3_MFMA) return fail(QD_EINVAL, "unknown mode");
   if (s->prec != QD_C64) return fail(QD_EDIM, "matrix-core modes need a complex64 state");
@@ -312,7 +315,7 @@ int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode) {
     int rc = launch_fused_block(s, f, int(b), mode);
     if (rc) return rc;
   }
-  return QD_OK;
+  return renorm ? normalize_on_device(s) : QD_OK;
 }
 
 void qd_fused_free(qd_fused* f) {

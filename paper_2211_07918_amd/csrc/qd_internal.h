@@ -191,6 +191,7 @@ int reduce_norm2_noalloc(const qd_state* s, double* out_dev);   // partials in a
 int reduce_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift,
                    double* norm2 = nullptr, double* fid_norm = nullptr);
 int scale_state(qd_state* s, double f);
+int normalize_on_device(qd_state* s);   // FP64 norm and scaling on the stream, no host wait
 
 // Free-group construction: role[i] = 0 free, 1 fixed (excluded), 2 singleton (own group with
 // lmul); qudits with index < lo or >= hi are ignored (treated as excluded).

@@ -184,6 +184,48 @@ int scale_state(qd_state* s, double f) {
   return QD_OK;
 }
 
+// Scaling by 1/sqrt(||psi||^2) with the squared norm read from device memory (FP64), so the whole
+// normalisation stays on the stream: a norm of zero or not finite leaves the state unchanged.
+template <typename R>
+__global__ __launch_bounds__(256) void k_scale_by_norm(R* psi_raw, uint64_t n, const double* norm2) {
+  using C = typename CxR<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_raw);
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const double n2 = *norm2;
+  if (i < n && n2 > 0.0 && isfinite(n2)) {
+    const double f = 1.0 / sqrt(n2);
+    C a = ld_stream(psi + i);
+    a.x = R(double(a.x) * f);
+    a.y = R(double(a.y) * f);
+    st_stream(psi + i, a);
+  }
+}
+
+int normalize_on_device(qd_state* s) {
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned g = red_grid(D);
+  int rc = ensure_red(s, g + 8);
+  if (rc) return rc;
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_norm_partial<double>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)s->data, D, s->red);
+  else
+    hipLaunchKernelGGL((k_norm_partial<float>), dim3(g), dim3(kRedBlock), 0, s->stream, (const float*)s->data, D, s->red);
+  hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(kRedBlock), 0, s->stream, s->red, g, 1, s->red + g);
+  QD_HIP(hipGetLastError());
+  for (uint64_t o = 0; o < D; o += kElemChunk) {
+    const uint64_t n = std::min(kElemChunk, D - o);
+    const dim3 grid(unsigned((n + 255) / 256));
+    if (s->prec == QD_C128)
+      hipLaunchKernelGGL((k_scale_by_norm<double>), grid, dim3(256), 0, s->stream, (double*)s->data + 2 * o, n,
+                         (const double*)(s->red + g));
+    else
+      hipLaunchKernelGGL((k_scale_by_norm<float>), grid, dim3(256), 0, s->stream, (float*)s->data + 2 * o, n,
+                         (const double*)(s->red + g));
+    QD_HIP(hipGetLastError());
+  }
+  return QD_OK;
+}
+
 // |idx> : amplitude 1 at idx, 0 elsewhere (offset o of the launch's first amplitude)
 template <typename R>
 __global__ __launch_bounds__(256) void k_fill_basis(R* psi_raw, uint64_t n, uint64_t o, uint64_t idx) {

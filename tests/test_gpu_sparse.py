@@ -185,9 +185,12 @@ def test_norm_and_probabilities(stream):
         for g in circ.gates:
             Q.apply_circuit_gate_sparse(sp, g, dims)
         idx, amp = S.run_circuit(circ)
-        p = Q.qd_sparse_probabilities(sp)
+        p = Q.qd_sparse_probabilities(sp)            # per entry, in the library's list order
+        gi = Q.qd_sparse_download(sp)[0]
+        order = np.argsort(gi, kind="stable")
+        assert gi[order].tolist() == idx.tolist()
         want = amp.real * amp.real + amp.imag * amp.imag
-        assert np.array_equal(p, want)
+        assert np.array_equal(p[order], want)
         assert abs(Q.qd_sparse_norm2(sp) - S.norm2(amp)) <= 1e-14
     finally:
         Q.qd_sparse_free(sp)
