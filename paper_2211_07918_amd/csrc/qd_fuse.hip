@@ -330,6 +330,7 @@ void qd_fused_free(qd_fused* f) {
     if (d.tab_yh) (void)hipFree(d.tab_yh);
     if (d.tab_lmap) (void)hipFree(d.tab_lmap);
     if (d.tab_rowpos) (void)hipFree(d.tab_rowpos);
+    if (d.tab_rowpos_odd) (void)hipFree(d.tab_rowpos_odd);
     if (d.tab_colpos) (void)hipFree(d.tab_colpos);
   }
   delete f;

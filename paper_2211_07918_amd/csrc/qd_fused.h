@@ -34,8 +34,19 @@ struct FusedArgs {
   const int64_t* hoff;              // dH run offsets from the tile origin
   const int32_t* yh;                // window-local index contributed by each run
   const uint32_t* lmap;             // BL entries: (column << 16) | window-local index part
-  const int32_t* rowpos;            // KPAD / 2 entries: tile position of window index y (column 0)
+  const int32_t* rowpos;            // KPAD / 2 entries: tile position of window index y (column 0);
+                                    // fill 1: two tables, for a tile origin of even and of odd index
   const int32_t* colpos;            // 16 NTILES entries: tile position of column n (window index 0)
+  // How the rows kernel moves a tile between HBM and LDS:
+  //   fill 0: even run length, 16-byte units of two amplitudes (every run starts at an even index);
+  //   fill 1: odd run length, each run read as (BL + 1) / 2 aligned 16-byte units from the even
+  //           index at or below its start, so one spare amplitude per run is read (and never
+  //           written back): LDS keeps BL + 1 slots per run, the run at slot offset start & 1;
+  //   fill 2: odd run length where a spare read could leave the state's buffer: 4-byte units.
+  uint32_t fill;
+  uint32_t upr;                     // 16-byte units per run (fill 0, 1)
+  Magic32 upm;                      // division by upr
+  uint32_t ES;                      // LDS amplitude slots per tile: dH (BL + 1) with fill 1, else E
 };
 
 struct FusedBlockDev {
@@ -48,6 +59,7 @@ struct FusedBlockDev {
   int32_t* tab_yh = nullptr;
   uint32_t* tab_lmap = nullptr;
   int32_t* tab_rowpos = nullptr;
+  int32_t* tab_rowpos_odd = nullptr;   // fill 1 (odd run length): tables for even and odd tile origins
   int32_t* tab_colpos = nullptr;
   double* u64 = nullptr;            // B x B complex FP64, row-major interleaved
   float* a32 = nullptr;             // Kp x Kp real embedding, FP32

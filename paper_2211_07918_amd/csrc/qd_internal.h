@@ -117,6 +117,7 @@ struct qd_state {
   qd::Register reg;
   int prec = QD_C128;
   void* data = nullptr;
+  int64_t cap_bytes = 0;      // bytes of device memory at data (the library pads its own by 16)
   bool owned = false;
   hipStream_t stream = nullptr;
   int device = 0;

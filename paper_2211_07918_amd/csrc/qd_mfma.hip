@@ -290,7 +290,7 @@ constexpr size_t kLdsBytes = 160 * 1024;   // floats after a tile: overshoot of 
 
 __host__ __device__ inline uint32_t rows_buf_floats(uint32_t E) { return (2u * E + kRowsSlack + 3u) & ~3u; }
 
-template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL>
 __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   constexpr int KPAD = 64 * MTW;
   constexpr int RY = KPAD / 2;
@@ -298,14 +298,15 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   static_assert(NTILES % NH == 0, "column tiles split evenly");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* xs = reinterpret_cast<float*>(lds_raw);
-  int32_t* s_rowpos = reinterpret_cast<int32_t*>(xs + rows_buf_floats(a.E));
-  int64_t* s_hoff = reinterpret_cast<int64_t*>(s_rowpos + RY);
+  int32_t* s_rowpos = reinterpret_cast<int32_t*>(xs + rows_buf_floats(a.ES));
+  int64_t* s_hoff = reinterpret_cast<int64_t*>(s_rowpos + 2 * RY);
   uint32_t* xw = reinterpret_cast<uint32_t*>(xs);   // BF16x3: amplitude e holds (hi, lo) at words 2e, 2e + 1
   float2* __restrict__ psi = a.psi;
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const uint32_t nrow = FILL == 1 ? 2u * RY : uint32_t(RY);
 
   for (uint32_t h = tid; h < a.dH; h += 256) s_hoff[h] = a.hoff[h];
-  for (uint32_t y = tid; y < uint32_t(RY); y += 256) s_rowpos[y] = a.rowpos[y];
+  for (uint32_t y = tid; y < nrow; y += 256) s_rowpos[y] = a.rowpos[y];
   // tile-local amplitude index of this lane's column in each column tile
   int32_t cp[NTILES];
 #pragma unroll
@@ -329,13 +330,24 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   }
   __syncthreads();
 
-  const bool pair = (a.BL & 1u) == 0;
-  const uint32_t E = a.E;
+  constexpr uint32_t odd = FILL == 1 ? 1u : 0u;
+  const uint32_t E = a.E, ES = a.ES;
+  // global amplitude index (below 2^32 on this path) of the first amplitude of 16-byte unit u of the
+  // tile whose origin is g0 (with fill 1 the unit may start one amplitude before its run, or end
+  // one after it); lo0: the offset of that amplitude inside its run
+  auto unit_addr = [&](uint32_t g0, uint32_t u, int32_t* lo0) -> uint32_t {
+    const uint32_t h = magic_div(u, a.upm), k = u - h * a.upr;
+    const uint32_t start = g0 + uint32_t(s_hoff[h]);
+    const uint32_t par = start & odd;
+    *lo0 = int32_t(2 * k) - int32_t(par);
+    return start - par + 2 * k;
+  };
   for (uint32_t tile = blockIdx.x; tile < a.tiles.count; tile += gridDim.x) {
     const int64_t g0 = fm_offset(a.tiles, tile);
+    const int32_t* rows = FILL == 1 ? s_rowpos + RY * (uint32_t(g0) & 1u) : s_rowpos;
     // ---- fill: LDS float f of the tile <- the amplitude's part in HBM (lane-consecutive LDS).
     // Batches of 8 copies per wave without bounds tests, so their run-offset lookups overlap.
-    if (pair) {
+    if constexpr (FILL == 0) {
       const uint32_t units = E >> 1;  // 16 bytes: two adjacent amplitudes of one run
       uint32_t u0 = w * 64;
       for (; u0 + 256 * 7 + 64 <= units; u0 += 256 * 8) {
@@ -358,6 +370,29 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         if (u < units) {
           const uint32_t e = 2 * u, h = magic_div(e, a.blm);
           src = psi + (g0 + s_hoff[h] + (e - h * a.BL));
+        }
+        __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, kNt);
+      }
+    } else if constexpr (FILL == 1) {
+      const uint32_t units = ES >> 1;  // 16 bytes: two adjacent amplitudes, 16-byte aligned
+      uint32_t u0 = w * 64;
+      for (; u0 + 256 * 7 + 64 <= units; u0 += 256 * 8) {
+        uint32_t ga[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int32_t lo0;
+          ga[j] = unit_addr(uint32_t(g0), u0 + 256 * j + l, &lo0);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the 8 lookups are in flight together
+#pragma unroll
+        for (int j = 0; j < 8; ++j) __builtin_amdgcn_global_load_lds(psi + ga[j], xs + 4 * (u0 + 256 * j), 16, 0, kNt);
+      }
+      for (; u0 < units; u0 += 256) {
+        const uint32_t u = u0 + l;
+        const float2* src = psi + (uint32_t(g0) - (uint32_t(g0) & odd));
+        if (u < units) {
+          int32_t lo0;
+          src = psi + unit_addr(uint32_t(g0), u, &lo0);
         }
         __builtin_amdgcn_global_load_lds(src, xs + 4 * u0, 16, 0, kNt);
       }
@@ -404,11 +439,11 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         *reinterpret_cast<uint2*>(xw + 2 * e) = o;
       };
       uint32_t base = 0;
-      for (; base + 256 * 4 <= E; base += 256 * 4) {
+      for (; base + 256 * 4 <= ES; base += 256 * 4) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) split1(base + tid + 256 * j);
       }
-      for (uint32_t e = base + tid; e < E; e += 256) split1(e);
+      for (uint32_t e = base + tid; e < ES; e += 256) split1(e);
       __syncthreads();
     }
 
@@ -425,7 +460,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         // Operand group g = (kk, t) is loaded one group ahead of its products (scheduling barriers
         // keep that order); the rows of K step kk + 1 are read at the start of K step kk.
         constexpr int G = KS * NTH;
-        const int32_t* rpl = s_rowpos + 4 * (l >> 4);
+        const int32_t* rpl = rows + 4 * (l >> 4);
         int4 rq[2];
         rq[0] = *reinterpret_cast<const int4*>(rpl);
         uint4 oh[2], ol[2];
@@ -464,7 +499,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         // The operands of K step kk + 1 are loaded before the products of step kk (scheduling
         // barriers keep that order).
         const float* xl = xs + ((l >> 4) & 1);
-        const int32_t* rpl = s_rowpos + (l >> 5);
+        const int32_t* rpl = rows + (l >> 5);
         float b[2][NTH];
         int32_t rk = 2 * rpl[0];
 #pragma unroll
@@ -491,7 +526,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         const uint32_t y0 = 8 * (w + 4 * i) + 2 * (l >> 4);   // result rows 2 y0 .. 2 y0 + 3
-        const int32_t r0 = 2 * s_rowpos[y0], r1 = 2 * s_rowpos[y0 + 1];
+        const int32_t r0 = 2 * rows[y0], r1 = 2 * rows[y0 + 1];
 #pragma unroll
         for (int t = 0; t < NTH; ++t) {
           const int nt = hf * NTH + t;
@@ -513,8 +548,42 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
       }
     }
     __syncthreads();
-    // ---- drain: the tile's E amplitudes back to their runs, batches of 8 per thread in flight
-    {
+    // ---- drain: the tile back to its runs, in batches per thread
+    if constexpr (FILL == 1) {
+      // 16-byte units; with fill 1 the units at the ends of a run store only their run's amplitude
+      constexpr int CH = BF ? 2 : 4;   // the BF16 split's A registers leave room for two in flight
+      const uint32_t units = ES >> 1;
+      const int32_t last = int32_t(a.BL) - 1;
+      auto store_unit = [&](uint32_t ga, int32_t lo0, uint4 v) {
+        if (lo0 >= 0 && lo0 < last) {
+          st_stream(reinterpret_cast<uint4*>(psi + ga), v);
+        } else if (lo0 < 0) {
+          st_stream(psi + ga + 1, float2{__uint_as_float(v.z), __uint_as_float(v.w)});
+        } else {
+          st_stream(psi + ga, float2{__uint_as_float(v.x), __uint_as_float(v.y)});
+        }
+      };
+      uint32_t base = 0;
+      for (; base + 256 * CH <= units; base += 256 * CH) {
+        uint4 v[CH];
+        uint32_t ga[CH];
+        int32_t lo0[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const uint32_t u = base + tid + 256 * j;
+          v[j] = *reinterpret_cast<const uint4*>(xs + 4 * u);
+          ga[j] = unit_addr(uint32_t(g0), u, &lo0[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // all LDS reads of the batch are in flight together
+#pragma unroll
+        for (int j = 0; j < CH; ++j) store_unit(ga[j], lo0[j], v[j]);
+      }
+      for (uint32_t u = base + tid; u < units; u += 256) {
+        int32_t lo0;
+        const uint32_t ga = unit_addr(uint32_t(g0), u, &lo0);
+        store_unit(ga, lo0, *reinterpret_cast<const uint4*>(xs + 4 * u));
+      }
+    } else {
       constexpr int CH = 8;
       auto store1 = [&](uint32_t e, float2 v) {
         const uint32_t h = magic_div(e, a.blm);
@@ -543,11 +612,12 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
 }
 
 static size_t rows_lds(const FusedArgs& a, int ry) {
-  return size_t(rows_buf_floats(a.E)) * sizeof(float) + size_t(ry) * sizeof(int32_t) + size_t(a.dH) * sizeof(int64_t);
+  return size_t(rows_buf_floats(a.ES)) * sizeof(float) + size_t(2 * ry) * sizeof(int32_t) +
+         size_t(a.dH) * sizeof(int64_t);
 }
 
-template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
-static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL>
+static int launch_rows_fill(const FusedArgs& a, hipStream_t st, int per_cu) {
   constexpr int RY = 32 * MTW;
   const size_t lds = rows_lds(a, RY);
   if (lds > kLdsBytes) return fail(QD_EINVAL, "fused tile exceeds the LDS of a CU");
@@ -555,11 +625,19 @@ static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(cus) * per_cu));
-  auto k = k_fused_rows<MTW, NTILES, NH, KS, BF, WPE>;
+  auto k = k_fused_rows<MTW, NTILES, NH, KS, BF, WPE, FILL>;
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
   QD_HIP(hipGetLastError());
   return QD_OK;
+}
+
+// one kernel instance per way of moving tiles (each keeps only its own copy code in registers)
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
+static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
+  if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0>(a, st, per_cu);
+  if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1>(a, st, per_cu);
+  return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 2>(a, st, per_cu);
 }
 
 template <int MTW, int NTILES, int KS, bool BF>
@@ -592,6 +670,13 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
   FusedArgs a = d.args;
   a.psi = reinterpret_cast<float2*>(s->data);
   if (a.tiles.count == 0) return QD_OK;
+  // the spare amplitude of an odd run may be the one after the last: read only inside the buffer
+  if (a.fill == 1 && (uint64_t(s->cap_bytes) < (uint64_t(s->reg.D) + 1) * 8u ||
+                      (reinterpret_cast<uintptr_t>(s->data) & 15u) != 0)) {
+    a.fill = 2;
+    a.ES = a.E;
+    a.rowpos = d.variant <= 3 ? d.tab_rowpos : nullptr;
+  }
   const bool bf = mode == QD_MODE_BF16X3_MFMA;
   if (a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
     switch (d.variant) {
@@ -728,6 +813,29 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
   QD_HIP(hipMemcpy(d->tab_colpos, colpos.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice));
   a.rowpos = d->variant <= 3 ? d->tab_rowpos : nullptr;
   a.colpos = d->tab_colpos;
+  // tile moves in 16-byte units: an odd run length keeps BL + 1 LDS slots per run, the run starting
+  // at slot (tile origin + run offset) & 1, so the row table depends on the origin's parity
+  if ((BL & 1u) == 0) {
+    a.fill = 0;
+    a.upr = uint32_t(BL / 2);
+    a.ES = a.E;
+  } else {
+    a.fill = 1;
+    a.upr = uint32_t((BL + 1) / 2);
+    a.ES = uint32_t(dH * (BL + 1));
+    std::vector<int32_t> rp2(2 * size_t(RY), 0);
+    for (int par = 0; par < 2; ++par)
+      for (int y = 0; y < RY; ++y) {
+        const int32_t pos = rowpos[y];                 // h BL + offset inside the run
+        const uint64_t h = uint64_t(pos) / BL, lo = uint64_t(pos) % BL;
+        const int32_t shift = int32_t((uint64_t(par) + uint64_t(hoff[h])) & 1u);
+        rp2[size_t(par) * RY + y] = int32_t(h * (BL + 1) + lo) + shift;
+      }
+    QD_HIP(hipMalloc((void**)&d->tab_rowpos_odd, sizeof(int32_t) * 2 * RY));
+    QD_HIP(hipMemcpy(d->tab_rowpos_odd, rp2.data(), sizeof(int32_t) * 2 * RY, hipMemcpyHostToDevice));
+    if (d->variant <= 3) a.rowpos = d->tab_rowpos_odd;
+  }
+  a.upm = make_magic32(a.upr);
   QD_HIP(hipMalloc((void**)&d->tab_hoff, sizeof(int64_t) * dH));
   QD_HIP(hipMalloc((void**)&d->tab_yh, sizeof(int32_t) * dH));
   QD_HIP(hipMalloc((void**)&d->tab_lmap, sizeof(uint32_t) * BL));

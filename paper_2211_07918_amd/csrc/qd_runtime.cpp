@@ -431,13 +431,16 @@ int qd_state_init(const int32_t* dims, int32_t n, int32_t prec, void* hip_stream
   qd_state* s = nullptr;
   int rc = new_state(dims, n, prec, hip_stream, &s);
   if (rc) return rc;
-  const size_t bytes = size_t(s->reg.D) * amp_bytes(prec);
+  // 16 spare bytes: a kernel may read one 16-byte unit that ends past the last amplitude (and never
+  // writes it)
+  const size_t bytes = size_t(s->reg.D) * amp_bytes(prec) + 16;
   hipError_t e = hipMalloc(&s->data, bytes);
   if (e != hipSuccess) {
     delete s;
     (void)hipGetLastError();
     return fail(QD_ENOMEM, "device allocation of the state failed (" + std::to_string(bytes) + " bytes)");
   }
+  s->cap_bytes = int64_t(bytes);
   s->owned = true;
   rc = launch_fill_basis(s, 0);
   if (rc) {
@@ -459,6 +462,7 @@ int qd_state_wrap(const int32_t* dims, int32_t n, int32_t prec, void* dev_ptr, i
     return fail(QD_EDIM, "wrapped buffer is smaller than the state");
   }
   s->data = dev_ptr;
+  s->cap_bytes = bytes;
   s->owned = false;
   *out = s;
   return QD_OK;

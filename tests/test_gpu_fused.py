@@ -252,3 +252,27 @@ def test_mode_and_register_errors(stream):
                 Q.qd_state_free(s)
     finally:
         Q.qd_fused_free(f)
+
+
+@pytest.mark.parametrize("mode", [Q.QD_MODE_FP32_MFMA, Q.QD_MODE_BF16X3_MFMA])
+def test_odd_runs_on_an_exact_size_buffer(stream, mode):
+    """Runs of odd length are moved in 16-byte units that read one spare amplitude past a run;
+    on a caller's buffer of exactly D amplitudes (no room past the last one) the tile moves fall
+    back to 4-byte units. Both give the same bits."""
+    import torch
+    circ = C.config3(9, 12)                                  # runs of 81 amplitudes, D = 19683 (odd)
+    f = fuse(circ, 81, stream)
+    try:
+        own = run_fused(circ, f, Q.QD_C64, mode, stream)
+        buf = torch.zeros(circ.D, dtype=torch.complex64, device="cuda")
+        s = Q.qd_state_wrap(circ.dims, Q.QD_C64, buf.data_ptr(), circ.D * 8, stream)
+        try:
+            Q.qd_state_set_basis(s, [0] * len(circ.dims))
+            Q.qd_apply_fused(s, f, mode)
+            wrapped = Q.qd_state_download(s)
+        finally:
+            Q.qd_state_free(s)
+    finally:
+        Q.qd_fused_free(f)
+    assert np.array_equal(own, wrapped)
+    assert precision(O.run_circuit(circ), own)[2] <= 1e-6
