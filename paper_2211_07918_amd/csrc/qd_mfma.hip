@@ -290,7 +290,10 @@ constexpr size_t kLdsBytes = 160 * 1024;   // floats after a tile: overshoot of 
 
 __host__ __device__ inline uint32_t rows_buf_floats(uint32_t E) { return (2u * E + kRowsSlack + 3u) & ~3u; }
 
-template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL>
+// LEFT (FP32): the tile's last column tile holds one column only (81 columns in 6 tiles of 16). Its
+// MFMA products are skipped; that column is computed on the vector units from the A rows each lane
+// already holds, the four lanes of a row summed by wavefront shuffles.
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL, bool LEFT>
 __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   constexpr int KPAD = 64 * MTW;
   constexpr int RY = KPAD / 2;
@@ -484,13 +487,15 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
           __builtin_amdgcn_sched_barrier(0);
           const v8bf bh = __builtin_bit_cast(v8bf, oh[g & 1]);
           const v8bf bl = __builtin_bit_cast(v8bf, ol[g & 1]);
+          if (!(LEFT && hf == NH - 1 && t == NTH - 1)) {
 #pragma unroll
-          for (int i = 0; i < MTW; ++i) {
-            v4f c = acc[i][t];
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i][kk], bh, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bl, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bh, c, 0, 0, 0);
-            acc[i][t] = c;
+            for (int i = 0; i < MTW; ++i) {
+              v4f c = acc[i][t];
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i][kk], bh, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bl, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i][kk], bh, c, 0, 0, 0);
+              acc[i][t] = c;
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -515,9 +520,11 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int t = 0; t < NTH; ++t)
+            if (!(LEFT && hf == NH - 1 && t == NTH - 1)) {
 #pragma unroll
-            for (int i = 0; i < MTW; ++i)
-              acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b[kk & 1][t], acc[i][t], 0, 0, 0);
+              for (int i = 0; i < MTW; ++i)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b[kk & 1][t], acc[i][t], 0, 0, 0);
+            }
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         for (int t = 0; t < NTH; ++t) {
           const int nt = hf * NTH + t;
           const uint32_t n = 16 * nt + (l & 15);
-          if (n < a.NT) {
+          if (!(LEFT && nt == NTILES - 1) && n < a.NT) {
             float2 v;
             if (y0 < uint32_t(a.twoB / 2)) {
               v.x = acc[i][t][0];
@@ -548,6 +555,36 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
       }
     }
     __syncthreads();
+    if constexpr (LEFT) {
+      // the single column of the last column tile: lane (row r = 16 (w + 4 i) + (l & 15)) sums
+      // A[r][k] x[k] over its own k (those of its A registers), then the four lanes of the row
+      const int32_t cl = a.colpos[16 * (NTILES - 1)];
+      float part[MTW];
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) part[i] = 0.f;
+      static_assert(!BF, "the single-column path is FP32 only");
+      const float* xl = xs + ((l >> 4) & 1);
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {   // real k = 4 kk + (l >> 4): complex row 2 kk + (l >> 5)
+        const float x = xl[2 * (rows[2 * kk + int(l >> 5)] + cl)];
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][kk], x, part[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        part[i] += __shfl_xor(part[i], 16);
+        part[i] += __shfl_xor(part[i], 32);
+      }
+      __syncthreads();   // every wave has read the column
+      if ((l >> 4) == 0) {
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+          const uint32_t r = 16 * (w + 4 * i) + (l & 15);
+          if (r < uint32_t(a.twoB)) xs[2 * (rows[r >> 1] + cl) + (r & 1)] = part[i];
+        }
+      }
+      __syncthreads();
+    }
     // ---- drain: the tile back to its runs, in batches per thread
     if constexpr (FILL == 1) {
       // 16-byte units; with fill 1 the units at the ends of a run store only their run's amplitude
@@ -616,7 +653,7 @@ static size_t rows_lds(const FusedArgs& a, int ry) {
          size_t(a.dH) * sizeof(int64_t);
 }
 
-template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL>
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL, bool LEFT>
 static int launch_rows_fill(const FusedArgs& a, hipStream_t st, int per_cu) {
   constexpr int RY = 32 * MTW;
   const size_t lds = rows_lds(a, RY);
@@ -625,7 +662,7 @@ static int launch_rows_fill(const FusedArgs& a, hipStream_t st, int per_cu) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(cus) * per_cu));
-  auto k = k_fused_rows<MTW, NTILES, NH, KS, BF, WPE, FILL>;
+  auto k = k_fused_rows<MTW, NTILES, NH, KS, BF, WPE, FILL, LEFT>;
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
   QD_HIP(hipGetLastError());
@@ -635,9 +672,18 @@ static int launch_rows_fill(const FusedArgs& a, hipStream_t st, int per_cu) {
 // one kernel instance per way of moving tiles (each keeps only its own copy code in registers)
 template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
 static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
-  if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0>(a, st, per_cu);
-  if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1>(a, st, per_cu);
-  return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 2>(a, st, per_cu);
+  // the single-column path only where the matrix cores bound the kernel (FP32, B <= 81); the BF16
+  // kernels are bound by their tile copies, and rebuilding A from its BF16 pair there spills
+  if constexpr (NTILES == 6 && !BF && KS == 41) {
+    if (a.NT == 16 * (NTILES - 1) + 1) {
+      if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0, true>(a, st, per_cu);
+      if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1, true>(a, st, per_cu);
+      return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 2, true>(a, st, per_cu);
+    }
+  }
+  if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0, false>(a, st, per_cu);
+  if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1, false>(a, st, per_cu);
+  return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 2, false>(a, st, per_cu);
 }
 
 template <int MTW, int NTILES, int KS, bool BF>
