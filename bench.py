@@ -646,9 +646,11 @@ def bench_batch(Q, torch, ncirc=4096, serial=True, cpu_seconds=10.0):
     reps = 3
 
     def graph_ms(w):
+        Q.qd_batch_compose_ms(b)               # drop the timings of earlier recordings
         Q.qd_batch_capture(b, True)
-        Q.qd_batch_apply_layers(b, flat, L, w)
+        Q.qd_batch_apply_layers(b, flat, L, w)  # the compositions run here, once, in FP64 on the GPU
         Q.qd_batch_capture(b, False)
+        comp = Q.qd_batch_compose_ms(b)
         Q.qd_batch_replay(b)
         torch.cuda.synchronize()
         e0.record()
@@ -656,11 +658,15 @@ def bench_batch(Q, torch, ncirc=4096, serial=True, cpu_seconds=10.0):
             Q.qd_batch_replay(b)
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps, comp
 
-    ms1 = graph_ms(1)
-    ms = graph_ms(width) if width != 1 else ms1
+    ms1, _ = graph_ms(1)
+    ms, compose_ms = graph_ms(width) if width != 1 else (ms1, 0.0)
     Q.qd_batch_free(b)
+    import tempfile
+    tpath = os.path.join(tempfile.gettempdir(), "qd_tune_batch.json")
+    Q.qd_tune_save(tpath)
+    keys = [json.loads(line.rstrip(",\n")) for line in open(tpath) if '"batch_key"' in line]
     one_s = None
     if serial:
         # one by one: every gate of every circuit through qd_apply_gate on its own state
@@ -678,6 +684,7 @@ def bench_batch(Q, torch, ncirc=4096, serial=True, cpu_seconds=10.0):
     launches, nbytes = batch_schedule(circs, width)
     cpu = oracle_rate(circs[:64], cpu_seconds, "a seeded 64-circuit subset of the same 4096") if cpu_seconds else None
     return {"cpu_oracle": cpu, "circuits": ncirc, "layers": L, "sum_D": int(sum(c.D for c in circs)), "graph_ms": ms,
+            "compose_ms_gpu_fp64": compose_ms, "tuned_keys": [k for k in keys if k["spt"]],
             "fusion_width": width, "graph_ms_width1": ms1, "launches": launches,
             "algorithmic_bytes": nbytes, "hbm_GBps": nbytes / (ms * 1e-3) / 1e9,
             "amp_upd_per_s": upd / (ms * 1e-3), "gates_per_s": ncirc * L / (ms * 1e-3),
@@ -894,6 +901,7 @@ def main():
         extras["batched_4096_circuits"] = bench_batch(Q, torch, serial=not args.batch_no_serial, cpu_seconds=cpu_s)
         bb = extras["batched_4096_circuits"]
         log(f"batched: {bb['graph_ms']:.1f} ms per 100 layers at fusion width {bb['fusion_width']} "
+            f"(compositions {bb['compose_ms_gpu_fp64']:.2f} ms on the GPU in FP64, at recording) "
             f"({bb['graph_ms_width1']:.1f} ms at width 1), {bb['amp_upd_per_s']:.3e} amp-upd/s, "
             f"{bb['hbm_GBps']:.0f} GB/s over {bb['launches']} launches"
             + (f", x{bb['speedup_vs_one_by_one']:.1f} vs one by one" if bb['speedup_vs_one_by_one'] else ""))

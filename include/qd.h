@@ -569,19 +569,37 @@ int qd_batch_apply_layer(qd_batch* b, const qd_gate* gates);
  * gates of each circuit fused into blocks: a block takes the circuit's next gates in order while
  * it has at most `width` of them (1..8; 0 = the tuned QD_TUNE_BATCH_FUSE) and the union of their
  * qudits (targets and controls) has at most 4 qudits of total dimension in {2..9, 12, 16, 18, 24,
- * 27, 32}. A
- * block of several gates is composed on the host in FP64 into one operation on that union (each
- * U embedded, the identity where its control misses) and applied in one pass over the state.
- * Launch i applies every circuit's i-th block, so the launch count is the most blocks of any
- * circuit. Gates are validated as in qd_batch_apply_layer before any device work. Recorded into
- * the graph while capture is on. */
+ * 27, 32}. A block of several gates is composed on the GPU in FP64 into one operation on that
+ * union (M = U_last ... U_first, each U embedded, the identity where its control misses; cast to
+ * the state's precision at the end) and applied in one pass over the state. Launch i applies every
+ * circuit's i-th block, so the launch count is the most blocks of any circuit. Gates are validated
+ * as in qd_batch_apply_layer before any device work. While capture is on, the launches are
+ * recorded into the graph and the compositions run once, at recording (replays reuse the composed
+ * blocks). */
 int qd_batch_apply_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, int32_t width);
 
+/* Tuning of the batched layer kernel by operation key (S9's gate class, d_T and stride class):
+ * key = 6 g + 2 c + s with g = 0 for one gate, 1 for a composed block; c = 0 for d_T <= 4, 1 for
+ * d_T 5..9, 2 for d_T 12..32; s = 0 when the operation's smallest target stride is below 16
+ * amplitudes (one 128-byte line of complex64), else 1. spt is the slices per thread of that key's
+ * operations: 1, 2, 4 or 8, or 0 to use QD_TUNE_BATCH_SPT_MID / _WIDE and the default rule.
+ * qd_batch_autotune_layers tunes the keys that carry at least 3% of the workload's amplitude
+ * updates; qd_tune_save writes every key. QD_EINVAL for a key outside 0..11 or another value. */
+enum { QD_BATCH_KEYS = 12 };
+int qd_batch_tune_key_set(int32_t key, int32_t spt);
+int qd_batch_tune_key_get(int32_t key, int32_t* spt);
+
+/* GPU time (ms, HIP events) of the block compositions qd_batch_apply_layers has launched since
+ * the previous call (or since the batch was created). Synchronises with those compositions. */
+int qd_batch_compose_ms(qd_batch* b, double* ms);
+
 /* Fusion-width autotuner: records qd_batch_apply_layers over the given layers into a graph for
- * widths 1, 2, 3, 4, 6 and 8, times replays of each (host composition excluded) and keeps the
- * fastest as QD_TUNE_BATCH_FUSE; then, at that width, the slices per thread of each wide slice
- * class (QD_TUNE_BATCH_SPT_MID, then QD_TUNE_BATCH_SPT_WIDE: the rule, 1, 2, 4, 8). All are saved
- * by qd_tune_save. The arena is saved and restored and a graph the caller recorded is kept. Not
+ * widths 1, 2, 3, 4, 6 and 8, times replays of each (the compositions run at recording, outside
+ * the timed replays) and keeps the fastest as QD_TUNE_BATCH_FUSE; then, at that width, the slices
+ * per thread of each wide slice class (QD_TUNE_BATCH_SPT_MID, then QD_TUNE_BATCH_SPT_WIDE: the
+ * rule, 1, 2, 4, 8); then those of each operation key (qd_batch_tune_key_set) carrying at least 3%
+ * of the amplitude updates, in decreasing share, a change kept when it gains 1%. All are saved by
+ * qd_tune_save. The arena is saved and restored and a graph the caller recorded is kept. Not
  * allowed while recording. Synchronises. */
 int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers);
 

@@ -30,7 +30,8 @@ __all__ = [
     "QD_TUNE_DIRECT_BLOCK", "QD_TUNE_DIRECT_SPT", "QD_TUNE_TILE_BLOCK", "QD_TUNE_TILE_ELEMS",
     "QD_TUNE_DIAG_BLOCK", "QD_TUNE_BATCH_BLOCK", "QD_TUNE_BATCH_SPT", "QD_TUNE_FUSED_COLS", "QD_TUNE_RUN_MIN",
     "QD_TUNE_BATCH_GRID", "QD_TUNE_BATCH_FUSE", "QD_TUNE_BATCH_SPT_MID", "QD_TUNE_BATCH_SPT_WIDE",
-    "qd_batch_apply_layers", "qd_batch_autotune_layers",
+    "qd_batch_apply_layers", "qd_batch_autotune_layers", "qd_batch_compose_ms", "QD_BATCH_KEYS",
+    "qd_batch_tune_key_set", "qd_batch_tune_key_get",
     "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "QD_ROUTE_GEMM", "qd_gate_route",
     "qd_version", "qd_last_error", "qd_last_kernel", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
@@ -62,6 +63,7 @@ QD_GATE_X, QD_GATE_Z, QD_GATE_F, QD_GATE_I = 0, 1, 2, 3
 QD_CLASS_DENSE, QD_CLASS_MONOMIAL, QD_CLASS_DIAGONAL = 0, 1, 2
 QD_CHANNEL_DEPOLARIZING, QD_CHANNEL_DEPHASING, QD_CHANNEL_AMPLITUDE_DAMPING = 0, 1, 2
 QD_OP_GATE, QD_OP_CHANNEL = 0, 1
+QD_BATCH_KEYS = 12
 QD_ROUTE_DIRECT, QD_ROUTE_TILED, QD_ROUTE_DIAG, QD_ROUTE_GENERIC, QD_ROUTE_GEMM = 0, 1, 2, 3, 4
 (QD_TUNE_DIRECT_BLOCK, QD_TUNE_DIRECT_SPT, QD_TUNE_TILE_BLOCK, QD_TUNE_TILE_ELEMS, QD_TUNE_DIAG_BLOCK,
  QD_TUNE_BATCH_BLOCK, QD_TUNE_BATCH_SPT, QD_TUNE_FUSED_COLS, QD_TUNE_RUN_MIN, QD_TUNE_BATCH_GRID,
@@ -191,6 +193,9 @@ _SIGS = {
     "qd_tune_save": (C.c_int, [C.c_char_p]),
     "qd_batch_autotune": (C.c_int, [_P, C.POINTER(_Gate)]),
     "qd_batch_apply_layers": (C.c_int, [_P, C.POINTER(_Gate), C.c_int32, C.c_int32]),
+    "qd_batch_compose_ms": (C.c_int, [_P, _DP]),
+    "qd_batch_tune_key_set": (C.c_int, [C.c_int32, C.c_int32]),
+    "qd_batch_tune_key_get": (C.c_int, [C.c_int32, _I32P]),
     "qd_batch_autotune_layers": (C.c_int, [_P, C.POINTER(_Gate), C.c_int32]),
     "qd_stream_copy": (C.c_int, [_P, _P, C.c_int64, _P]),
 }
@@ -876,6 +881,23 @@ def qd_batch_apply_layer(b: int, gates):
 def qd_batch_apply_layers(b: int, gates, nlayers: int, width: int = 0):
     """gates: a GateArray of nlayers x ncirc slots (layer-major); width 0 = the tuned fusion width."""
     _check(load().qd_batch_apply_layers(_P(b), gates.arr, int(nlayers), int(width)))
+
+
+def qd_batch_compose_ms(b: int) -> float:
+    """GPU time of the block compositions launched since the previous call (ms)."""
+    v = C.c_double()
+    _check(load().qd_batch_compose_ms(_P(b), C.byref(v)))
+    return float(v.value)
+
+
+def qd_batch_tune_key_set(key: int, spt: int):
+    _check(load().qd_batch_tune_key_set(int(key), int(spt)))
+
+
+def qd_batch_tune_key_get(key: int) -> int:
+    v = C.c_int32()
+    _check(load().qd_batch_tune_key_get(int(key), C.byref(v)))
+    return int(v.value)
 
 
 def qd_batch_autotune_layers(b: int, gates, nlayers: int):

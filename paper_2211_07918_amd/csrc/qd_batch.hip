@@ -225,6 +225,74 @@ __global__ __launch_bounds__(256) void k_batch_ones(R* arena, const int64_t* off
   }
 }
 
+// ------------------------------------------------------------------------------------------ composition
+// A circuit's consecutive gates composed into one operation on the union Q of their qudits (at most
+// kBatchMaxTargets, d_Q <= kBatchMaxSlice): M = G_{w-1} ... G_0 in FP64 on the GPU, each G_i the gate
+// embedded on Q (U where its control holds its value, the identity elsewhere), written to the
+// launch's U pool in the state's precision. One workgroup per composed operation, M in LDS.
+struct ComposeJob {
+  uint32_t uoff;                    // offset of M in the launch's U pool (values of R)
+  int32_t dq;                       // d_Q
+  int32_t ng;                       // member gates, in circuit order
+  uint32_t g0;                      // first member in the gate table
+};
+struct ComposeGate {
+  int32_t tw;                       // weight of the target digit in Q's local index
+  int32_t dt;                       // target dimension
+  int32_t cw;                       // weight of the control digit, 0: no control
+  int32_t cd;                       // control dimension
+  int32_t cv;                       // control value
+  uint32_t u64;                     // offset of U (dt x dt complex FP64, interleaved) in the FP64 pool
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_compose(const ComposeJob* __restrict__ jobs,
+                                                       const ComposeGate* __restrict__ gates,
+                                                       const double* __restrict__ u64, R* __restrict__ pool) {
+  constexpr int kEnt = kBatchMaxSlice * kBatchMaxSlice / 256;   // entries of M per thread
+  __shared__ double2 M[kBatchMaxSlice * kBatchMaxSlice];
+  __shared__ double2 su[kBatchMaxDim * kBatchMaxDim];
+  const ComposeJob J = jobs[blockIdx.x];
+  const int dq = J.dq, n = dq * dq, tid = int(threadIdx.x);
+  for (int e = tid; e < n; e += 256) M[e] = double2{(e / dq == e % dq) ? 1.0 : 0.0, 0.0};
+  for (int gi = 0; gi < J.ng; ++gi) {
+    const ComposeGate G = gates[J.g0 + gi];
+    __syncthreads();   // M complete, su free
+    for (int e = tid; e < G.dt * G.dt; e += 256) su[e] = double2{u64[G.u64 + 2 * e], u64[G.u64 + 2 * e + 1]};
+    __syncthreads();
+    double2 nv[kEnt];
+#pragma unroll
+    for (int q = 0; q < kEnt; ++q) {
+      const int e = tid + 256 * q;
+      if (e >= n) continue;
+      const int x = e / dq, col = e - x * dq;
+      const int yt = (x / G.tw) % G.dt;                       // target digit of row x
+      nv[q] = M[e];
+      if (G.cw == 0 || (x / G.cw) % G.cd == G.cv) {
+        const int x0 = x - yt * G.tw;                         // row x with its target digit 0
+        double re = 0.0, im = 0.0;
+        for (int y = 0; y < G.dt; ++y) {
+          const double2 u = su[yt * G.dt + y], m = M[(x0 + y * G.tw) * dq + col];
+          re += u.x * m.x - u.y * m.y;
+          im += u.x * m.y + u.y * m.x;
+        }
+        nv[q] = double2{re, im};
+      }
+    }
+    __syncthreads();   // every row of M is read
+#pragma unroll
+    for (int q = 0; q < kEnt; ++q) {
+      const int e = tid + 256 * q;
+      if (e < n) M[e] = nv[q];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n; e += 256) {
+    pool[J.uoff + 2 * e] = R(M[e].x);
+    pool[J.uoff + 2 * e + 1] = R(M[e].y);
+  }
+}
+
 }  // namespace qd
 
 struct qd_batch {
@@ -243,6 +311,8 @@ struct qd_batch {
   hipGraphNode_t last = nullptr;
   std::vector<void*> layer_bufs;          // device buffers owned by recorded layers
   std::vector<std::vector<unsigned char>> layer_args;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> compose_ev;   // composition launches not yet timed
+  double compose_ms = 0.0;                // time of earlier composition launches already read back
 };
 
 namespace qd {
@@ -296,7 +366,8 @@ struct BatchOp {
   int32_t t[kBatchMaxTargets] = {};
   int m = 0;
   int32_t c = 0, v = 0;
-  std::vector<double> U;
+  std::vector<double> U;                  // one gate: its U
+  std::vector<const qd_gate*> members;    // composed (2 or more gates): composed on the GPU
 };
 
 static bool slice_supported(int dT) {
@@ -305,14 +376,23 @@ static bool slice_supported(int dT) {
 
 // Host: descriptors and U pool of one launch; *ntiles the total tile count, *maxdt the largest slice
 // of a composed operation (0 when the launch holds one-gate operations only).
+struct ComposeWork {                    // the composed operations of one launch
+  std::vector<ComposeJob> jobs;
+  std::vector<ComposeGate> gates;
+  std::vector<double> u64;
+};
+
 template <typename R>
 static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector<BatchDesc>* desc,
-                       std::vector<R>* pool, uint32_t* ntiles, int* maxdt) {
+                       std::vector<R>* pool, ComposeWork* cw, uint32_t* ntiles, int* maxdt) {
   *maxdt = 0;
   const uint32_t nc = uint32_t(b->regs.size());
   const TuneParams& tp = tune();
   desc->assign(nc, BatchDesc{});
   pool->clear();
+  cw->jobs.clear();
+  cw->gates.clear();
+  cw->u64.clear();
   uint64_t tiles = 0;
   for (uint32_t c = 0; c < nc; ++c) {
     const Register& r = b->regs[c];
@@ -359,9 +439,44 @@ static int build_layer(qd_batch* b, const std::vector<BatchOp>& ops, std::vector
     *maxdt = std::max(*maxdt, o.k == 1 ? 0 : dT);
     d.nwork = uint32_t(nwork);
     d.uoff = uint32_t(pool->size());
-    for (int i = 0; i < 2 * dT * dT; ++i) pool->push_back(R(o.U[size_t(i)]));
-    const int cls = dT >= 12 ? tp.batch_spt_wide : (dT >= 5 ? tp.batch_spt_mid : 0);   // tuned per slice class
-    d.spt = uint32_t(cls ? cls : std::min(tp.batch_spt, 2 * batch_kb(dT)));
+    if (o.members.empty()) {
+      for (int i = 0; i < 2 * dT * dT; ++i) pool->push_back(R(o.U[size_t(i)]));
+    } else {
+      // composed on the GPU into this slot: the weights of Q's digits (first most significant)
+      pool->resize(pool->size() + 2 * size_t(dT) * dT, R(0));
+      int wt[QD_MAX_QUDITS] = {};
+      {
+        int w = 1;
+        for (int j = o.k - 1; j >= 0; --j) {
+          wt[o.t[j]] = w;
+          w *= r.dims[o.t[j]];
+        }
+      }
+      ComposeJob J;
+      J.uoff = d.uoff;
+      J.dq = dT;
+      J.ng = int32_t(o.members.size());
+      J.g0 = uint32_t(cw->gates.size());
+      cw->jobs.push_back(J);
+      for (const qd_gate* g : o.members) {
+        ComposeGate G;
+        const int t = g->targets[0];
+        G.tw = wt[t];
+        G.dt = r.dims[t];
+        G.cw = g->m == 1 ? wt[g->controls[0]] : 0;
+        G.cd = g->m == 1 ? r.dims[g->controls[0]] : 1;
+        G.cv = g->m == 1 ? g->control_values[0] : 0;
+        G.u64 = uint32_t(cw->u64.size());
+        cw->u64.insert(cw->u64.end(), g->U, g->U + 2 * size_t(G.dt) * G.dt);
+        cw->gates.push_back(G);
+      }
+    }
+    // slices per thread: tuned per operation key, else per slice class, else the rule
+    int64_t smin = INT64_MAX;
+    for (int j = 0; j < o.k; ++j) smin = std::min<int64_t>(smin, r.strides[o.t[j]]);
+    const int kv = tp.batch_spt_key[batch_key(!o.members.empty(), dT, smin)];
+    const int cls = dT >= 12 ? tp.batch_spt_wide : (dT >= 5 ? tp.batch_spt_mid : 0);
+    d.spt = uint32_t(kv ? kv : (cls ? cls : std::min(tp.batch_spt, 2 * batch_kb(dT))));
     const uint64_t tile_slices = uint64_t(tp.batch_block) * d.spt;
     tiles += (nwork + tile_slices - 1) / tile_slices;
     if (tiles > 0xFFFFFFF0ull) return fail(QD_EOVERFLOW, "too many tiles in one layer");
@@ -414,55 +529,6 @@ static bool gate_union(const Register& r, const qd_gate* const* gs, int w, int* 
   return slice_supported(dQ);
 }
 
-// The gates gs[0..w) of one circuit composed on the union Q of their qudits (ascending, first most
-// significant): M = G_{w-1} ... G_0 in FP64, each G_i the gate embedded on Q (U where its control
-// holds its value, the identity elsewhere), applied to the columns of M one target slice at a time.
-// False when Q has more than kBatchMaxTargets qudits or its dimension is not a supported slice size.
-static bool compose_ops(const Register& r, const qd_gate* const* gs, int w, BatchOp* out) {
-  int Q[2 * kBatchMaxFuse];
-  int nq = 0, dQ = 0;
-  if (!gate_union(r, gs, w, Q, &nq, &dQ)) return false;
-  auto pos = [&](int q) { return int(std::find(Q, Q + nq, q) - Q); };
-  int wt[kBatchMaxTargets];   // weight of each Q digit in the local index
-  wt[nq - 1] = 1;
-  for (int j = nq - 2; j >= 0; --j) wt[j] = wt[j + 1] * r.dims[Q[j + 1]];
-  std::vector<double> M(2 * size_t(dQ) * dQ, 0.0);
-  for (int i = 0; i < dQ; ++i) M[2 * (size_t(i) * dQ + i)] = 1.0;
-  double col[2 * kBatchMaxDim];
-  for (int i = 0; i < w; ++i) {
-    const qd_gate& g = *gs[i];
-    const int t = pos(g.targets[0]), dt = r.dims[g.targets[0]], wt_t = wt[t];
-    const int cpos = g.m == 1 ? pos(g.controls[0]) : -1;
-    for (int x0 = 0; x0 < dQ; ++x0) {        // x0: local index whose target digit is 0
-      if ((x0 / wt_t) % dt != 0) continue;
-      if (cpos >= 0 && (x0 / wt[cpos]) % r.dims[g.controls[0]] != g.control_values[0]) continue;
-      for (int bb = 0; bb < dQ; ++bb) {      // rows x0 + y wt_t of column bb <- U times them
-        for (int y = 0; y < dt; ++y) {
-          const size_t e = 2 * (size_t(x0 + y * wt_t) * dQ + bb);
-          col[2 * y] = M[e];
-          col[2 * y + 1] = M[e + 1];
-        }
-        for (int y = 0; y < dt; ++y) {
-          double re = 0.0, im = 0.0;
-          for (int x = 0; x < dt; ++x) {
-            const double ur = g.U[2 * (y * dt + x)], ui = g.U[2 * (y * dt + x) + 1];
-            re += ur * col[2 * x] - ui * col[2 * x + 1];
-            im += ur * col[2 * x + 1] + ui * col[2 * x];
-          }
-          const size_t e = 2 * (size_t(x0 + y * wt_t) * dQ + bb);
-          M[e] = re;
-          M[e + 1] = im;
-        }
-      }
-    }
-  }
-  out->k = nq;
-  for (int j = 0; j < nq; ++j) out->t[j] = Q[j];
-  out->m = 0;
-  out->U = std::move(M);
-  return true;
-}
-
 // The next block of circuit c's gates, from layer *cursor on (empty slots skipped): consecutive
 // gates while the block has at most W of them and they compose on at most kBatchMaxTargets qudits
 // with a supported slice size; a block of one gate stays that gate. *cursor moves past the block;
@@ -489,26 +555,74 @@ static void next_block(const qd_batch* b, uint32_t c, const qd_gate* gates, int3
   }
   *cursor = l;
   *out = BatchOp();
-  if (n == 1) *out = op_of(b, c, *cur[0]);
-  else if (n > 1) (void)compose_ops(r, cur, n, out);   // fits: checked as the block grew
+  if (n == 1) {
+    *out = op_of(b, c, *cur[0]);
+  } else if (n > 1) {   // fits one slice: checked as the block grew; composed on the GPU in FP64
+    int Q[2 * kBatchMaxFuse], nq = 0, dQ = 0;
+    (void)gate_union(r, cur, n, Q, &nq, &dQ);
+    out->k = nq;
+    for (int j = 0; j < nq; ++j) out->t[j] = Q[j];
+    out->members.assign(cur, cur + n);
+  }
 }
 
 template <typename R>
 static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   std::vector<BatchDesc> desc;
   std::vector<R> pool;
+  ComposeWork cw;
   uint32_t ntiles = 0;
   int maxdt = 0;
-  int rc = build_layer<R>(b, ops, &desc, &pool, &ntiles, &maxdt);
+  int rc = build_layer<R>(b, ops, &desc, &pool, &cw, &ntiles, &maxdt);
   if (rc) return rc;
+  auto pad256 = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t dbytes = desc.size() * sizeof(BatchDesc);
   const size_t pbytes = std::max<size_t>(pool.size(), 1) * sizeof(R);
-  const size_t dpad = (dbytes + 255) / 256 * 256;
-  const size_t ppad = (pbytes + 255) / 256 * 256;
-  std::vector<unsigned char> blob(dpad + ppad + std::max<size_t>(ntiles, 1) * sizeof(uint32_t), 0);
+  const size_t dpad = pad256(dbytes);
+  const size_t ppad = pad256(pbytes);
+  const size_t tpad = pad256(std::max<size_t>(ntiles, 1) * sizeof(uint32_t));
+  const size_t jpad = pad256(cw.jobs.size() * sizeof(ComposeJob));
+  const size_t gpad = pad256(cw.gates.size() * sizeof(ComposeGate));
+  const size_t upad = pad256(cw.u64.size() * sizeof(double));
+  std::vector<unsigned char> blob(dpad + ppad + tpad + jpad + gpad + upad, 0);
   std::memcpy(blob.data(), desc.data(), dbytes);
   if (!pool.empty()) std::memcpy(blob.data() + dpad, pool.data(), pool.size() * sizeof(R));
   uint32_t* tmap = reinterpret_cast<uint32_t*>(blob.data() + dpad + ppad);   // tile -> circuit
+  unsigned char* cbase = blob.data() + dpad + ppad + tpad;
+  if (!cw.jobs.empty()) {
+    std::memcpy(cbase, cw.jobs.data(), cw.jobs.size() * sizeof(ComposeJob));
+    std::memcpy(cbase + jpad, cw.gates.data(), cw.gates.size() * sizeof(ComposeGate));
+    std::memcpy(cbase + jpad + gpad, cw.u64.data(), cw.u64.size() * sizeof(double));
+  }
+  // the composed operations of the launch, built in FP64 on the GPU into the launch's U pool
+  // before the layer runs (timed with events, read back by qd_batch_compose_ms)
+  auto compose = [&](unsigned char* dev) -> int {
+    if (cw.jobs.empty()) return QD_OK;
+    const size_t c0 = dpad + ppad + tpad;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->compose_ev.size() >= 1024) {   // fold older timings so the event list stays bounded
+      for (auto& ev : b->compose_ev) {
+        float t = 0.f;
+        QD_HIP(hipEventSynchronize(ev.second));
+        QD_HIP(hipEventElapsedTime(&t, ev.first, ev.second));
+        b->compose_ms += t;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+      }
+      b->compose_ev.clear();
+    }
+    QD_HIP(hipEventCreate(&e0));
+    QD_HIP(hipEventCreate(&e1));
+    b->compose_ev.emplace_back(e0, e1);
+    QD_HIP(hipEventRecord(e0, b->stream));
+    hipLaunchKernelGGL((k_batch_compose<R>), dim3(unsigned(cw.jobs.size())), dim3(256), 0, b->stream,
+                       reinterpret_cast<const ComposeJob*>(dev + c0),
+                       reinterpret_cast<const ComposeGate*>(dev + c0 + jpad),
+                       reinterpret_cast<const double*>(dev + c0 + jpad + gpad), reinterpret_cast<R*>(dev + dpad));
+    QD_HIP(hipGetLastError());
+    QD_HIP(hipEventRecord(e1, b->stream));
+    return QD_OK;
+  };
   for (uint32_t c = 0; c < uint32_t(desc.size()); ++c) {
     const uint32_t end = c + 1 < uint32_t(desc.size()) ? desc[c + 1].tile0 : ntiles;
     for (uint32_t t = desc[c].tile0; t < end; ++t) tmap[t] = c;
@@ -530,6 +644,8 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
     void* dev_blob = nullptr;
     rc = ring_push_stream(&b->ring, b->stream, blob.data(), blob.size(), &dev_blob);
     if (rc) return rc;
+    rc = compose(static_cast<unsigned char*>(dev_blob));
+    if (rc) return rc;
     a.desc = reinterpret_cast<const BatchDesc*>(dev_blob);
     a.upool = reinterpret_cast<const R*>(static_cast<unsigned char*>(dev_blob) + dpad);
     a.tmap = reinterpret_cast<const uint32_t*>(static_cast<unsigned char*>(dev_blob) + dpad + ppad);
@@ -547,6 +663,8 @@ static int apply_layer_t(qd_batch* b, const std::vector<BatchOp>& ops) {
   QD_HIP(hipMalloc(&buf, blob.size()));
   b->layer_bufs.push_back(buf);
   QD_HIP(hipMemcpy(buf, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  rc = compose(static_cast<unsigned char*>(buf));   // once, at recording: replays reuse the blocks
+  if (rc) return rc;
   if (ntiles == 0) return QD_OK;
   a.desc = reinterpret_cast<const BatchDesc*>(buf);
   a.upool = reinterpret_cast<const R*>(static_cast<unsigned char*>(buf) + dpad);
@@ -754,6 +872,32 @@ int qd_batch_autotune(qd_batch* b, const qd_gate* gates) {
 }  // extern "C"
 
 namespace qd {
+// Amplitude updates per operation key of the blocks the layers form at fusion width W (host only).
+static void key_shares(const qd_batch* b, const qd_gate* gates, int32_t nlayers, int W, double* share) {
+  const uint32_t nc = uint32_t(b->regs.size());
+  double tot = 0.0;
+  for (int k = 0; k < QD_BATCH_KEYS; ++k) share[k] = 0.0;
+  for (uint32_t c = 0; c < nc; ++c) {
+    const Register& r = b->regs[c];
+    int32_t cursor = 0;
+    for (;;) {
+      BatchOp o;
+      next_block(b, c, gates, nlayers, W, &cursor, &o);
+      if (o.k == 0) break;
+      int dT = 1;
+      int64_t smin = INT64_MAX;
+      for (int j = 0; j < o.k; ++j) {
+        dT *= r.dims[o.t[j]];
+        smin = std::min<int64_t>(smin, r.strides[o.t[j]]);
+      }
+      const double upd = double(r.D) / (o.m == 1 ? double(r.dims[o.c]) : 1.0);
+      share[batch_key(!o.members.empty(), dT, smin)] += upd;
+      tot += upd;
+    }
+  }
+  for (int k = 0; k < QD_BATCH_KEYS; ++k) share[k] = tot > 0.0 ? share[k] / tot : 0.0;
+}
+
 // Record the layers at fusion width w into the batch's graph, replay it once, then time two replays.
 static int time_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers, int w, hipEvent_t e0, hipEvent_t e1,
                        float* ms, hipError_t* e) {
@@ -819,6 +963,31 @@ int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers)
     }
     *knob = (rc || e != hipSuccess) ? keep : best_v;
   }
+  // then each operation key that carries at least 3% of the amplitude updates at that width, in
+  // decreasing share (a change must gain 1%: keys a workload lacks stay as they are)
+  {
+    double share[QD_BATCH_KEYS];
+    key_shares(b, gates, nlayers, best_w, share);
+    int order[QD_BATCH_KEYS];
+    for (int k = 0; k < QD_BATCH_KEYS; ++k) order[k] = k;
+    std::sort(order, order + QD_BATCH_KEYS, [&](int x, int y) { return share[x] > share[y]; });
+    for (int k : order) {
+      if (share[k] < 0.03) break;
+      const int keep = tp.batch_spt_key[k];
+      int best_v = keep;
+      for (int v : {0, 1, 2, 4, 8}) {
+        if (rc || e != hipSuccess || v == keep) continue;
+        tp.batch_spt_key[k] = v;
+        float ms = 0.f;
+        rc = time_layers(b, gates, nlayers, best_w, e0, e1, &ms, &e);
+        if (!rc && e == hipSuccess && ms < 0.99f * best) {
+          best = ms;
+          best_v = v;
+        }
+      }
+      tp.batch_spt_key[k] = (rc || e != hipSuccess) ? keep : best_v;
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   hipError_t e2 = hipMemcpyAsync(b->arena, save, bytes, hipMemcpyDeviceToDevice, b->stream);
@@ -832,9 +1001,32 @@ int qd_batch_autotune_layers(qd_batch* b, const qd_gate* gates, int32_t nlayers)
   return QD_OK;
 }
 
+int qd_batch_compose_ms(qd_batch* b, double* ms) {
+  if (!b || !ms) return fail(QD_EINVAL, "null argument");
+  double tot = b->compose_ms;
+  b->compose_ms = 0.0;
+  hipError_t err = hipSuccess;
+  for (auto& ev : b->compose_ev) {
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventSynchronize(ev.second);
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, ev.first, ev.second);
+    tot += t;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  b->compose_ev.clear();
+  if (err != hipSuccess) return hip_fail(err, "batch composition timing");
+  *ms = tot;
+  return QD_OK;
+}
+
 void qd_batch_free(qd_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (auto& ev : b->compose_ev) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   free_graph(b);
   if (b->arena) (void)hipFree(b->arena);
   if (b->offs_dev) (void)hipFree(b->offs_dev);

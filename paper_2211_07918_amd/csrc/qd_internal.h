@@ -55,10 +55,14 @@ struct TuneParams {
   int batch_fuse = 1;       // gates composed into one batched operation (qd_batch_apply_layers, width 0)
   int batch_spt_mid = 0;    // slices per thread of batched slices of 5..9 amplitudes (0: two load batches)
   int batch_spt_wide = 0;   // slices per thread of batched slices of 12 to 32 amplitudes (0: as above)
+  // batched slices per thread by (gate class, slice class, stride class), 0: the value above
+  int batch_spt_key[QD_BATCH_KEYS] = {};
   int fused_cols = 64;      // slice columns per fused-block tile
   int run_min = 16;         // a target stride below this routes the gate to the LDS tile kernel
 };
 TuneParams& tune();
+// key of a batched operation: composed (2+ gates) or one gate, slice size d_T, smallest target stride
+int batch_key(bool composed, int dT, int64_t min_stride);
 
 // Autotuned tile shape per (precision, stride class of the gate's smallest target stride).
 constexpr int kStrideBuckets = 5;   // strides 1 | 2-3 | 4-15 | 16-255 | >= 256

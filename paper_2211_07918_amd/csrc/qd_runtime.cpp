@@ -29,6 +29,11 @@ TuneParams& tune() {
   return t;
 }
 
+int batch_key(bool composed, int dT, int64_t min_stride) {
+  const int c = dT <= 4 ? 0 : (dT <= 9 ? 1 : 2);
+  return 6 * (composed ? 1 : 0) + 2 * c + (min_stride < 16 ? 0 : 1);
+}
+
 // ------------------------------------------------------------------------------------------ register
 int make_register(const int32_t* dims, int32_t n, Register* r) {
   if (!dims || !r) return fail(QD_EINVAL, "null dims");
@@ -670,6 +675,21 @@ int qd_tune_set(int32_t param, int32_t value) {
     default:
       return fail(QD_EINVAL, "unknown tuning parameter");
   }
+}
+
+int qd_batch_tune_key_set(int32_t key, int32_t spt) {
+  if (key < 0 || key >= QD_BATCH_KEYS) return fail(QD_EINVAL, "batch tuning key must be 0..11");
+  if (spt != 0 && spt != 1 && spt != 2 && spt != 4 && spt != 8)
+    return fail(QD_EINVAL, "batch slices per thread must be 0 (inherit), 1, 2, 4 or 8");
+  tune().batch_spt_key[key] = spt;
+  return QD_OK;
+}
+
+int qd_batch_tune_key_get(int32_t key, int32_t* spt) {
+  if (!spt) return fail(QD_EINVAL, "null output");
+  if (key < 0 || key >= QD_BATCH_KEYS) return fail(QD_EINVAL, "batch tuning key must be 0..11");
+  *spt = tune().batch_spt_key[key];
+  return QD_OK;
 }
 
 int qd_tune_get(int32_t param, int32_t* value) {

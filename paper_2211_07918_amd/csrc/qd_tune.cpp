@@ -68,9 +68,17 @@ static int write_table(const char* path) {
   const TuneParams& tp = tune();
   std::fprintf(f,
                "%s{\"batch_block\": %d, \"batch_spt\": %d, \"batch_grid\": %d, \"batch_fuse\": %d, "
-               "\"batch_spt_mid\": %d, \"batch_spt_wide\": %d}\n]\n",
+               "\"batch_spt_mid\": %d, \"batch_spt_wide\": %d}",
                first ? "" : ",\n", tp.batch_block, tp.batch_spt, tp.batch_wpc, tp.batch_fuse, tp.batch_spt_mid,
                tp.batch_spt_wide);
+  // slices per thread of the batched kernel per operation key (0: inherited)
+  static const char* gate_cls[2] = {"one gate", "composed"};
+  static const char* slice_cls[3] = {"2-4", "5-9", "12-32"};
+  static const char* stride_cls[2] = {"< 16", ">= 16"};
+  for (int k = 0; k < QD_BATCH_KEYS; ++k)
+    std::fprintf(f, ",\n{\"batch_key\": %d, \"gate\": \"%s\", \"d_T\": \"%s\", \"min_stride\": \"%s\", \"spt\": %d}", k,
+                 gate_cls[k / 6], slice_cls[(k / 2) % 3], stride_cls[k % 2], tp.batch_spt_key[k]);
+  std::fprintf(f, "\n]\n");
   std::fclose(f);
   return QD_OK;
 }
@@ -136,9 +144,22 @@ int qd_tune_load(const char* path) {
   if (!f) return fail(QD_EINVAL, std::string("cannot read ") + path);
   TuneEntry tab[2][kStrideBuckets] = {};
   int batch_block = 0, batch_spt = 0, batch_grid = 0, batch_fuse = 0, spt_mid = 0, spt_wide = 0, n = 0;
+  int key_spt[QD_BATCH_KEYS] = {};
   char line[512];
   while (std::fgets(line, sizeof(line), f)) {
-    int p, b, tiled, block, spt, te;
+    int p, b, tiled, block, spt, te, key;
+    if (std::sscanf(line, " {\"batch_key\": %d,", &key) == 1) {
+      const char* sp = std::strstr(line, "\"spt\": ");
+      int v = -1;
+      if (!sp || std::sscanf(sp, "\"spt\": %d", &v) != 1 || key < 0 || key >= QD_BATCH_KEYS ||
+          (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)) {
+        std::fclose(f);
+        return fail(QD_EINVAL, "batch key entry out of range");
+      }
+      key_spt[key] = v;
+      ++n;
+      continue;
+    }
     if (std::sscanf(line, " {\"prec\": %d, \"bucket\": %d, \"tiled\": %d, \"block\": %d, \"spt\": %d, \"tile_elems\": %d}",
                     &p, &b, &tiled, &block, &spt, &te) == 6) {
       if (p < 0 || p > 1 || b < 0 || b >= kStrideBuckets || (block != 64 && block != 128 && block != 192 && block != 256) ||
@@ -175,6 +196,7 @@ int qd_tune_load(const char* path) {
     tp.batch_spt_mid = spt_mid;
     tp.batch_spt_wide = spt_wide;
   }
+  for (int k = 0; k < QD_BATCH_KEYS; ++k) tune().batch_spt_key[k] = key_spt[k];
   return QD_OK;
 }
 

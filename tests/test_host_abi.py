@@ -318,3 +318,29 @@ def test_batch_create_rejects_before_device_work():
         with pytest.raises(Q.QDError) as e:
             Q.qd_batch_create(dims_list, prec, 0)
         assert e.value.code == code, (dims_list, prec)
+
+
+def test_batch_tuning_keys(tmp_path):
+    """Per-key slices per thread of the batched kernel: range checks, and a save / load round trip
+    that keeps every key."""
+    keep = [Q.qd_batch_tune_key_get(k) for k in range(Q.QD_BATCH_KEYS)]
+    try:
+        for bad_key, v in ((-1, 2), (Q.QD_BATCH_KEYS, 2)):
+            with pytest.raises(Q.QDError):
+                Q.qd_batch_tune_key_set(bad_key, v)
+        with pytest.raises(Q.QDError):
+            Q.qd_batch_tune_key_set(0, 3)
+        want = [(0, 1, 2, 4, 8)[k % 5] for k in range(Q.QD_BATCH_KEYS)]
+        for k, v in enumerate(want):
+            Q.qd_batch_tune_key_set(k, v)
+        path = str(tmp_path / "t.json")
+        Q.qd_tune_save(path)
+        text = open(path).read()
+        assert '"batch_key": 11, "gate": "composed", "d_T": "12-32", "min_stride": ">= 16"' in text
+        for k in range(Q.QD_BATCH_KEYS):
+            Q.qd_batch_tune_key_set(k, 0)
+        Q.qd_tune_load(path)
+        assert [Q.qd_batch_tune_key_get(k) for k in range(Q.QD_BATCH_KEYS)] == want
+    finally:
+        for k, v in enumerate(keep):
+            Q.qd_batch_tune_key_set(k, v)
