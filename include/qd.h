@@ -94,6 +94,11 @@ const char* qd_last_error(void);
  * thread-local storage, for profiling labels; it changes no state. */
 const char* qd_last_kernel(void);
 
+/* Gate kernel launches made on a state since it was created: one per qd_apply_gate that moved
+ * data, and one per pass of the density-matrix calls (a composed run of operations is one pass).
+ * Host counter, no synchronisation. QD_EINVAL for a null argument. */
+int qd_state_gate_launches(const qd_state* s, int64_t* out);
+
 /* Register table (Sec. 2.2: the state has prod dims[i] entries). Host only, no device work.
  * Writes D to *D_out and the n big-endian strides to strides_out[n] (caller-allocated).
  * QD_EINVAL for n outside 1..64 or null pointers, QD_EDIM for a radix outside 2..256,
@@ -525,7 +530,10 @@ typedef struct {
  * controls together span qudits S with prod d_S <= 4 (a gate and the channels that follow it, a
  * qubit-controlled gate on a qubit and its channel, operations on two qubits) is composed on the
  * host in FP64: each operation embedded on S (a gate as its controlled unitary, the identity
- * elsewhere), then one pass of the product superoperator on (S, S + n). Asynchronous. */
+ * elsewhere), then one pass of the product superoperator on (S, S + n). Asynchronous.
+ * A call that fails validation leaves rho unchanged; an allocation or launch failure in a later
+ * pass of a call (QD_ENOMEM, QD_EDEVICE) can leave rho with the earlier passes applied, as can such
+ * a failure in the second pass of a two-pass qd_density_apply_gate. */
 int qd_density_apply_ops(qd_state* rho, const qd_density_op* ops, int32_t count, uint32_t flags);
 
 /* tr(rho) (both parts), fixed reduction order. Synchronises. */

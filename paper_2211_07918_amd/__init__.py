@@ -33,7 +33,7 @@ __all__ = [
     "qd_batch_apply_layers", "qd_batch_autotune_layers", "qd_batch_compose_ms", "QD_BATCH_KEYS",
     "qd_batch_tune_key_set", "qd_batch_tune_key_get",
     "QD_ROUTE_DIRECT", "QD_ROUTE_TILED", "QD_ROUTE_DIAG", "QD_ROUTE_GENERIC", "QD_ROUTE_GEMM", "qd_gate_route",
-    "qd_version", "qd_last_error", "qd_last_kernel", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
+    "qd_version", "qd_last_error", "qd_last_kernel", "qd_state_gate_launches", "qd_register_strides", "qd_gate_matrix", "qd_validate_gate",
     "qd_gate_class", "qd_state_init", "qd_state_wrap", "qd_state_set_basis", "qd_state_upload",
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
@@ -118,6 +118,7 @@ _SIGS = {
     "qd_state_dims": (C.c_int, [_P, _I32P, _I32P]),
     "qd_state_precision": (C.c_int, [_P, _I32P]),
     "qd_state_device_ptr": (C.c_int, [_P, C.POINTER(_P)]),
+    "qd_state_gate_launches": (C.c_int, [_P, _I64P]),
     "qd_state_sync": (C.c_int, [_P]),
     "qd_state_free": (None, [_P]),
     "qd_apply_gate": (C.c_int, [_P, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _DP]),
@@ -347,6 +348,12 @@ def qd_state_download(s: int) -> np.ndarray:
     out = np.empty(qd_state_size(s), dtype=_state_dtype(s))
     _check(load().qd_state_download(_P(s), out.ctypes.data_as(_P), out.size))
     return out
+
+
+def qd_state_gate_launches(s: int) -> int:
+    v = C.c_int64()
+    _check(load().qd_state_gate_launches(_P(s), C.byref(v)))
+    return int(v.value)
 
 
 def qd_state_device_ptr(s: int) -> int:

@@ -6,11 +6,11 @@
 // doubled register dims ++ dims: row qudits 0..n-1, column qudits n..2n-1, so element (x, y) sits
 // at flat index x * D + y (row-major). With this layout
 //   * a gate G maps rho -> G rho G^dagger, i.e. G on the row qudits and conj(G) on the column
-//     qudits. With G embedded on its targets and controls (dimension d_G = d_T x d_C), a gate with
-//     d_G <= kFuseGate (dense U; kFuseGateFree without controls), d_G <= kFuseMono (diagonal U, or
-//     monomial U without controls) or d_G <= kFuseMonoCtl (monomial U with controls) is one pass of
-//     G (x) conj(G) over (T, C, T + n, C + n); other gates take two passes (U on T with its
-//     controls, conj(U) on T + n with the shifted controls);
+//     qudits. With G embedded on its targets and controls (dimension d_G = d_T x d_C), a diagonal
+//     gate with d_G <= kOnePass and an uncontrolled gate with d_T <= kOnePass are one pass of
+//     G (x) conj(G) over (T, C, T + n, C + n); every other gate (in particular every controlled gate
+//     that is not diagonal) takes two passes: U on T with its controls, conj(U) on T + n with the
+//     shifted controls, each over the elements whose control digits match;
 //   * a channel with Kraus operators K_1..K_r maps rho -> sum_k K_k rho K_k^dagger, one pass of the
 //     superoperator S = sum_k K_k (x) conj(K_k) over (T, T + n);
 //   * consecutive operations whose targets and controls together span qudits Sq of dimension
@@ -32,17 +32,14 @@ namespace qd {
 namespace dm {
 
 constexpr int kBlock = 256;
-// d_G (targets x controls) up to which a gate is one pass of G (x) conj(G): the superoperator must
-// stay on kernels that beat two passes. Dense superoperators up to 9 x 9 run on the slice kernels;
-// a dense 16 x 16 one takes the GEMM route (0.82-0.86 ms on 1.07e8 elements), which beats two full
-// passes (2 x 0.57 ms) but not the two passes of a controlled gate, which touch only the elements
-// whose control digits match (2 x 0.36 ms with a qubit control); monomial and diagonal ones up to
-// 16 x 16, except a controlled permutation: its 16 x 16 pass (0.71 ms) loses to the two passes over
-// the matching elements (about 0.62 ms), as the dense case does.
-constexpr int kFuseGate = 3;          // dense U
-constexpr int kFuseGateFree = 4;      // dense U without controls
-constexpr int kFuseMono = 4;          // diagonal U, or monomial U without controls
-constexpr int kFuseMonoCtl = 3;       // monomial U with controls
+// d_G (targets x controls) up to which a gate is one pass of G (x) conj(G). An uncontrolled gate on
+// d_T <= 4 gives a superoperator of at most 16 x 16, one pass that beats two full ones. A controlled
+// gate (d_G >= 4) that is not diagonal stays at two passes: each touches only the elements whose
+// control digits match (2 x 0.36 ms with a qubit control on 1.07e8 elements), while its 16 x 16
+// superoperator needs a full pass of more work per element (0.66-0.71 ms measured for the dense and
+// the permutation cases). Diagonal superoperators cost one elementwise pass, so a diagonal gate is
+// one pass whenever d_G <= 4.
+constexpr int kOnePass = 4;
 constexpr int kMaxChannelDim = 32;    // d_T of a channel (its superoperator is d_T^2 x d_T^2 <= 1024)
 constexpr int kFuseGroup = 4;         // dimension of the qudits a run of operations touches, up to which it is one pass
 constexpr int kRedGrid = 1024;
@@ -295,9 +292,7 @@ int qd_density_apply_gate(qd_state* rho, const int32_t* targets, int32_t k, cons
   const int dG = dT * dC;                 // the gate embedded on (targets, controls)
   const uint32_t skip = flags | QD_FLAG_SKIP_UNITARY_CHECK;
   const int cls = classify(U, dT);
-  const bool one_pass = cls == QD_CLASS_DIAGONAL ? dG <= kFuseMono
-                        : cls == QD_CLASS_MONOMIAL ? dG <= (m == 0 ? kFuseMono : kFuseMonoCtl)
-                                                   : dG <= (m == 0 ? kFuseGateFree : kFuseGate);
+  const bool one_pass = cls == QD_CLASS_DIAGONAL ? dG <= kOnePass : (m == 0 && dT <= kOnePass);
   if (one_pass) {
     // one pass of G (x) conj(G) over (T, C, T + n, C + n), G[(t, c), (t', c')] = delta(c, c') times
     // U[t][t'] when the control digits c hold the control values, else delta(t, t')

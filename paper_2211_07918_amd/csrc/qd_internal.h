@@ -131,6 +131,7 @@ struct qd_state {
   void* mws = nullptr;        // measurement workspace (sums of weights, marginal partials, staging)
   size_t mws_cap = 0;         // in bytes
   int dens_n = 0;             // density matrix over dens_n qudits (register = dims ++ dims), else 0
+  int64_t launches = 0;       // gate kernel launches made on the state (passes, for a density matrix)
 };
 
 namespace qd {

@@ -548,7 +548,15 @@ int qd_apply_gate_ex(qd_state* s, const int32_t* targets, int32_t k, const int32
   if (rc) return rc;
   GatePlan p;
   plan_gate(s->reg, s->prec, targets, k, controls, control_values, m, U, &p);
-  return launch_gate(s, p);
+  rc = launch_gate(s, p);
+  if (rc == QD_OK && last_kernel()[0]) ++s->launches;
+  return rc;
+}
+
+int qd_state_gate_launches(const qd_state* s, int64_t* out) {
+  if (!s || !out) return fail(QD_EINVAL, "null argument");
+  *out = s->launches;
+  return QD_OK;
 }
 
 int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,

@@ -279,6 +279,43 @@ def test_runs_across_targets_compose_and_match(stream, prec):
         ga, gb = download_rho(a, dims), download_rho(b, dims)
         assert np.max(np.abs(ga - want)) <= tol and np.max(np.abs(gb - want)) <= tol
         assert abs(np.trace(ga) - 1.0) <= tol
+        # the runs were composed: one pass per run of operations spanning dimension <= 4, against
+        # one or two passes per operation when applied one call at a time
+        composed, single = expected_passes(ops, dims)
+        assert (composed, single) == (10, 19)
+        assert Q.qd_state_gate_launches(a) == composed and Q.qd_state_gate_launches(b) == single
     finally:
         Q.qd_state_free(a)
         Q.qd_state_free(b)
+
+
+def expected_passes(ops, dims):
+    """Passes of qd_density_apply_ops and of one call per operation, by the documented rules: a
+    run of two or more consecutive operations whose qudits span dimension <= 4 is one pass; alone,
+    a channel is one pass, a gate one pass when diagonal with d_G <= 4 or uncontrolled with
+    d_T <= 4, else two."""
+    def qudits(o):
+        return set(o[1].targets) | set(o[1].controls) if o[0] == "gate" else set(o[1])
+
+    def span(qs):
+        return int(np.prod([dims[q] for q in qs])) if qs else 1
+
+    def alone(o):
+        if o[0] != "gate":
+            return 1
+        g = o[1]
+        dT = span(g.targets)
+        dG = dT * span(g.controls)
+        diag = Q.qd_gate_class(Q.gate_unitary(g, dims)) == Q.QD_CLASS_DIAGONAL
+        return 1 if (diag and dG <= 4) or (not g.controls and dT <= 4) else 2
+
+    composed, i = 0, 0
+    while i < len(ops):
+        qs, j = qudits(ops[i]), i + 1
+        if span(qs) <= 4:
+            while j < len(ops) and span(qs | qudits(ops[j])) <= 4:
+                qs |= qudits(ops[j])
+                j += 1
+        composed += alone(ops[i]) if j - i == 1 else 1
+        i = j
+    return composed, sum(alone(o) for o in ops)
