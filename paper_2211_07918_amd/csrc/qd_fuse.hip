@@ -332,6 +332,7 @@ void qd_fused_free(qd_fused* f) {
     if (d.tab_rowpos) (void)hipFree(d.tab_rowpos);
     if (d.tab_rowpos_odd) (void)hipFree(d.tab_rowpos_odd);
     if (d.tab_colpos) (void)hipFree(d.tab_colpos);
+    if (d.tab_wrow) (void)hipFree(d.tab_wrow);
   }
   delete f;
 }

@@ -36,7 +36,10 @@ struct FusedArgs {
   const uint32_t* lmap;             // BL entries: (column << 16) | window-local index part
   const int32_t* rowpos;            // KPAD / 2 entries: tile position of window index y (column 0);
                                     // fill 1: two tables, for a tile origin of even and of odd index
-  const int32_t* colpos;            // 16 NTILES entries: tile position of column n (window index 0)
+  const int32_t* colpos;            // 16 NTILES entries: tile position of column n (window index 0),
+                                    // also its offset in HBM from the start of the run
+  const uint32_t* wrow;             // KPAD / 2 entries: HBM offset of amplitude (y, column 0) from
+                                    // the tile origin, so (y, n) sits at origin + wrow[y] + colpos[n]
   // How the rows kernel moves a tile between HBM and LDS:
   //   fill 0: even run length, 16-byte units of two amplitudes (every run starts at an even index);
   //   fill 1: odd run length, each run read as (BL + 1) / 2 aligned 16-byte units from the even
@@ -61,6 +64,7 @@ struct FusedBlockDev {
   int32_t* tab_rowpos = nullptr;
   int32_t* tab_rowpos_odd = nullptr;   // fill 1 (odd run length): tables for even and odd tile origins
   int32_t* tab_colpos = nullptr;
+  uint32_t* tab_wrow = nullptr;
   double* u64 = nullptr;            // B x B complex FP64, row-major interleaved
   float* a32 = nullptr;             // Kp x Kp real embedding, FP32
   __hip_bfloat16* ahi = nullptr;    // BF16 split of a32: hi

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
         ahi[i][kk] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(a.ahi + size_t(row) * KPAD + k0));
         alo[i][kk] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(a.alo + size_t(row) * KPAD + k0));
       } else {
-        af[i][kk] = a.a32[size_t(row) * KPAD + 4 * kk + (l >> 4)];
+        af[i][kk] = a.a32[size_t(row) * KPAD + 2 * (4 * (kk >> 1) + int(l >> 4)) + (kk & 1)];
       }
     }
   }
@@ -500,30 +500,35 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
           __builtin_amdgcn_sched_barrier(0);
         }
       } else {
-        // lane: column n = 16 nt + (l & 15), row y = 2 kk + (l >> 5), part c = (l >> 4) & 1.
-        // The operands of K step kk + 1 are loaded before the products of step kk (scheduling
-        // barriers keep that order).
-        const float* xl = xs + ((l >> 4) & 1);
-        const int32_t* rpl = rows + (l >> 5);
-        float b[2][NTH];
-        int32_t rk = 2 * rpl[0];
+        // K in pairs of steps: in steps 2 j and 2 j + 1 lane l takes the real and the imaginary
+        // part of amplitude (row y = 4 j + (l >> 4), column n = 16 nt + (l & 15)), one 8-byte LDS
+        // read for two products. The operands of pair j + 1 are loaded before the products of
+        // pair j (scheduling barriers keep that order).
+        static_assert(KS % 2 == 0, "K steps in pairs");
+        constexpr int KP = KS / 2;
+        const float2* x2 = reinterpret_cast<const float2*>(xs);
+        const int32_t* rpl = rows + (l >> 4);
+        float2 b[2][NTH];
+        int32_t rk = rpl[0];
 #pragma unroll
-        for (int t = 0; t < NTH; ++t) b[0][t] = xl[rk + 2 * cp[hf * NTH + t]];
-        rk = 2 * rpl[2];
+        for (int t = 0; t < NTH; ++t) b[0][t] = x2[rk + cp[hf * NTH + t]];
+        rk = rpl[4];
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk) {
-          if (kk + 1 < KS) {
+        for (int j = 0; j < KP; ++j) {
+          if (j + 1 < KP) {
 #pragma unroll
-            for (int t = 0; t < NTH; ++t) b[(kk + 1) & 1][t] = xl[rk + 2 * cp[hf * NTH + t]];
-            if (kk + 2 < KS) rk = 2 * rpl[2 * (kk + 2)];
+            for (int t = 0; t < NTH; ++t) b[(j + 1) & 1][t] = x2[rk + cp[hf * NTH + t]];
+            if (j + 2 < KP) rk = rpl[4 * (j + 2)];
           }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int t = 0; t < NTH; ++t)
             if (!(LEFT && hf == NH - 1 && t == NTH - 1)) {
 #pragma unroll
-              for (int i = 0; i < MTW; ++i)
-                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], b[kk & 1][t], acc[i][t], 0, 0, 0);
+              for (int i = 0; i < MTW; ++i) {
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j], b[j & 1][t].x, acc[i][t], 0, 0, 0);
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j + 1], b[j & 1][t].y, acc[i][t], 0, 0, 0);
+              }
             }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -563,12 +568,12 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
 #pragma unroll
       for (int i = 0; i < MTW; ++i) part[i] = 0.f;
       static_assert(!BF, "the single-column path is FP32 only");
-      const float* xl = xs + ((l >> 4) & 1);
+      const float2* x2 = reinterpret_cast<const float2*>(xs);
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {   // real k = 4 kk + (l >> 4): complex row 2 kk + (l >> 5)
-        const float x = xl[2 * (rows[2 * kk + int(l >> 5)] + cl)];
+      for (int j = 0; j < KS / 2; ++j) {   // complex row 4 j + (l >> 4): real rows 2 (4 j + (l >> 4)) + c
+        const float2 x = x2[rows[4 * j + int(l >> 4)] + cl];
 #pragma unroll
-        for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][kk], x, part[i]);
+        for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][2 * j + 1], x.y, fmaf(af[i][2 * j], x.x, part[i]));
       }
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
@@ -674,7 +679,7 @@ template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE>
 static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
   // the single-column path only where the matrix cores bound the kernel (FP32, B <= 81); the BF16
   // kernels are bound by their tile copies, and rebuilding A from its BF16 pair there spills
-  if constexpr (NTILES == 6 && !BF && KS == 41) {
+  if constexpr (NTILES == 6 && !BF && KS == 42) {
     if (a.NT == 16 * (NTILES - 1) + 1) {
       if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0, true>(a, st, per_cu);
       if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1, true>(a, st, per_cu);
@@ -684,6 +689,309 @@ static int launch_rows(const FusedArgs& a, hipStream_t st, int per_cu) {
   if (a.fill == 0) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 0, false>(a, st, per_cu);
   if (a.fill == 1) return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 1, false>(a, st, per_cu);
   return launch_rows_fill<MTW, NTILES, NH, KS, BF, WPE, 2, false>(a, st, per_cu);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Double-buffered tiles: one workgroup of 8 waves per CU with two tile buffers in LDS. Waves w and
+// w + 4 (one SIMD) hold the same rows of A and take the two halves of the column tiles, so every
+// SIMD has two waves of products. Per tile p, every wave
+//   issues the loads of tile p + 1 into the other buffer (no wait), runs its products of tile p,
+//   waits for its loads (BF16x3: splits the amplitudes it loaded itself), stores its results of
+//   tile p from the accumulators straight to HBM, and meets the others at one barrier;
+// so the loads of the next tile are in flight during the products, and the stores are issued after
+// the wait (the stores of tile p complete while tile p + 1 is worked on; vector memory counters
+// would otherwise make the wait for the loads also wait for them).
+__host__ __device__ inline uint32_t pipe_in_floats(uint32_t ES) { return (2u * ES + 255u) & ~255u; }
+
+// Tile moves by all 512 threads (thread t: wave t / 64, lane t % 64).
+template <int FILL>
+__device__ __forceinline__ void pipe_fill_tile(const FusedArgs& a, float2* __restrict__ psi, float* xs, const int64_t* s_hoff,
+                                          int64_t g0, uint32_t w, uint32_t l) {
+  constexpr uint32_t odd = FILL == 1 ? 1u : 0u;
+  if constexpr (FILL == 0 || FILL == 1) {
+    const uint32_t units = (FILL == 0 ? a.E : a.ES) >> 1;   // 16 bytes: two adjacent amplitudes
+    auto addr = [&](uint32_t u) -> uint32_t {   // global amplitude index of unit u's first amplitude
+      if constexpr (FILL == 0) {
+        const uint32_t e = 2 * u, h = magic_div(e, a.blm);
+        return uint32_t(g0 + s_hoff[h]) + (e - h * a.BL);
+      } else {
+        const uint32_t h = magic_div(u, a.upm), k = u - h * a.upr;
+        const uint32_t start = uint32_t(g0) + uint32_t(s_hoff[h]);
+        return start - (start & odd) + 2 * k;
+      }
+    };
+    uint32_t u0 = w * 64;
+    for (; u0 + 512 * 3 + 64 <= units; u0 += 512 * 4) {
+      uint32_t ga[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ga[j] = addr(u0 + 512 * j + l);
+      __builtin_amdgcn_sched_barrier(0);   // the lookups are in flight together
+#pragma unroll
+      for (int j = 0; j < 4; ++j) __builtin_amdgcn_global_load_lds(psi + ga[j], xs + 4 * (u0 + 512 * j), 16, 0, kNt);
+    }
+    for (; u0 < units; u0 += 512) {
+      const uint32_t u = u0 + l;
+      // lanes past the end read the tile's first unit again (inside the state) into the slack
+      const uint32_t ga = addr(u < units ? u : 0u);
+      __builtin_amdgcn_global_load_lds(psi + ga, xs + 4 * u0, 16, 0, kNt);
+    }
+  } else {
+    const uint32_t units = a.E * 2;   // 4 bytes: one part of one amplitude
+    const float* pf = reinterpret_cast<const float*>(psi);
+    auto addr = [&](uint32_t f) -> uint64_t {
+      const uint32_t e = f >> 1, h = magic_div(e, a.blm);
+      return 2 * uint64_t(g0 + s_hoff[h] + (e - h * a.BL)) + (f & 1u);
+    };
+    uint32_t u0 = w * 64;
+    for (; u0 + 512 * 3 + 64 <= units; u0 += 512 * 4) {
+      uint64_t ga[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ga[j] = addr(u0 + 512 * j + l);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) __builtin_amdgcn_global_load_lds(pf + ga[j], xs + u0 + 512 * j, 4, 0, kNt);
+    }
+    for (; u0 < units; u0 += 512) {
+      const uint32_t f = u0 + l;
+      const uint64_t ga = addr(f < units ? f : 0u);
+      __builtin_amdgcn_global_load_lds(pf + ga, xs + u0, 4, 0, kNt);
+    }
+  }
+}
+
+// The products of one wave over one tile: its MTW row tiles of A times its NTH column tiles of X,
+// except the (row tile i, column tile t) pairs whose bit t MTW + i is set in SKIPM. `between` runs
+// after the first operands are read and before the products (the next tile's loads: issued after
+// those reads, they make no read of this tile wait for them).
+template <int MTW, uint32_t SKIPM>
+__host__ __device__ constexpr bool pp_on(int i, int t) { return ((SKIPM >> (t * MTW + i)) & 1u) == 0; }
+template <int MTW, uint32_t SKIPM>
+__host__ __device__ constexpr bool pp_tile(int t) {
+  bool any = false;
+  for (int i = 0; i < MTW; ++i) any = any || pp_on<MTW, SKIPM>(i, t);
+  return any;
+}
+
+template <int MTW, int NTH, int KS, uint32_t SKIPM, typename F>
+__device__ __forceinline__ void pipe_products(v4f (&acc)[MTW][NTH], const float* xs, const int32_t* rows,
+                                              const int32_t (&cp)[NTH], const float (&af)[MTW][KS], uint32_t l,
+                                              F&& between) {
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
+  // K in pairs of steps: in steps 2 j and 2 j + 1 lane l takes the real and the imaginary part
+  // of amplitude (row y = 4 j + (l >> 4), column n = 16 nt + (l & 15)), one 8-byte LDS read for
+  // two products. The operands of pair j + 1 are loaded before the products of pair j.
+  static_assert(KS % 2 == 0, "K steps in pairs");
+  constexpr int KP = KS / 2;
+  const float2* x2 = reinterpret_cast<const float2*>(xs);
+  const int32_t* rpl = rows + (l >> 4);
+  float2 b[2][NTH];
+  int32_t rk = rpl[0];
+#pragma unroll
+  for (int t = 0; t < NTH; ++t)
+    if (pp_tile<MTW, SKIPM>(t)) b[0][t] = x2[rk + cp[t]];
+  rk = rpl[4];
+  between();
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    if (j + 1 < KP) {
+#pragma unroll
+      for (int t = 0; t < NTH; ++t)
+        if (pp_tile<MTW, SKIPM>(t)) b[(j + 1) & 1][t] = x2[rk + cp[t]];
+      if (j + 2 < KP) rk = rpl[4 * (j + 2)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < NTH; ++t)
+#pragma unroll
+      for (int i = 0; i < MTW; ++i)
+        if (pp_on<MTW, SKIPM>(i, t)) {
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j], b[j & 1][t].x, acc[i][t], 0, 0, 0);
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j + 1], b[j & 1][t].y, acc[i][t], 0, 0, 0);
+        }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Column tiles of the two waves of a SIMD (wave half hf = w / 4). Without the single column:
+// NTILES / 2 each. With it (81 columns: tiles 0-4 on the matrix cores, tile 5 = column 80 on the
+// vector units), balanced as 8 and 7 products per K step: half 0 takes tiles 0, 1 and the first
+// two row tiles of tile 2; half 1 the last row tile of tile 2, tiles 3, 4 and the single column.
+template <int MTW, int NTILES, bool LEFT>
+struct PipeSplit {
+  static constexpr bool BAL = LEFT && MTW == 3 && NTILES == 6;
+  static constexpr int NT0 = BAL ? 3 : NTILES / 2, NT1 = BAL ? 4 : NTILES / 2;
+  static constexpr int CB1 = BAL ? 2 : NTILES / 2;   // first column tile of half 1
+  static constexpr uint32_t M0 = BAL ? (1u << (2 * MTW + 2)) : 0u;
+  static constexpr uint32_t M1 = BAL ? ((1u << 0) | (1u << 1) | (((1u << MTW) - 1u) << (3 * MTW)))
+                                     : (LEFT ? (((1u << MTW) - 1u) << ((NT1 - 1) * MTW)) : 0u);
+  static constexpr int NTMAX = NT0 > NT1 ? NT0 : NT1;
+};
+
+// One tile of the double-buffered kernel (tile p from xs, tile p + 1 into xn) for wave half H. The
+// restrict qualifiers tell the compiler the two buffers are distinct, so it does not wait for the
+// loads into xn before the products read xs (the loads are issued after the first operand reads).
+template <int MTW, int NTILES, int KS, int FILL, bool LEFT, int H>
+__device__ __forceinline__ void pipe_phase(const FusedArgs& a, float* __restrict__ xs, float* __restrict__ xn,
+                                           uint32_t p, uint32_t ntile, const int64_t* s_hoff,
+                                           const int32_t* s_rowpos, const uint32_t* s_wrow,
+                                           const int32_t (&cpa)[PipeSplit<MTW, NTILES, LEFT>::NTMAX],
+                                           const float (&af)[MTW][KS], int32_t cl, uint32_t w, uint32_t l) {
+  using S = PipeSplit<MTW, NTILES, LEFT>;
+  constexpr int RY = 32 * MTW;
+  constexpr int NTH = H ? S::NT1 : S::NT0;
+  constexpr uint32_t M = H ? S::M1 : S::M0;
+  constexpr int CB = H ? S::CB1 : 0;
+  constexpr bool LC = LEFT && H == 1;   // this half computes the single column
+  float2* __restrict__ psi = a.psi;
+  const uint32_t q = w & 3u;
+  const uint32_t g0 = uint32_t(fm_offset(a.tiles, blockIdx.x + p * gridDim.x));
+  const int32_t* rows = s_rowpos + (FILL == 1 ? RY * int32_t(g0 & 1u) : 0);
+  int32_t cp[NTH];
+#pragma unroll
+  for (int t = 0; t < NTH; ++t) cp[t] = cpa[t];
+
+  v4f acc[MTW][NTH];
+  pipe_products<MTW, NTH, KS, M>(acc, xs, rows, cp, af, l, [&] {
+    if (p + 1 < ntile)
+      pipe_fill_tile<FILL>(a, psi, xn, s_hoff, fm_offset(a.tiles, blockIdx.x + (p + 1) * gridDim.x), w, l);
+  });
+  float part[MTW];
+  if constexpr (LC) {
+    // the single column on the vector units: lane (row 16 (q + 4 i) + (l & 15)) sums A[r][k] x[k]
+    // over its own k, then the four lanes of the row by wavefront shuffles
+    const float2* x2 = reinterpret_cast<const float2*>(xs);
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) part[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KS / 2; ++j) {   // complex row 4 j + (l >> 4): real rows 2 (4 j + (l >> 4)) + c
+      const float2 x = x2[rows[4 * j + int(l >> 4)] + cl];
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][2 * j + 1], x.y, fmaf(af[i][2 * j], x.x, part[i]));
+    }
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      part[i] += __shfl_xor(part[i], 16);
+      part[i] += __shfl_xor(part[i], 32);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // this lane's loads of tile p + 1 (and the stores of tile p - 1)
+  // results of tile p from the accumulators to HBM: amplitude (y, n) at g0 + wrow[y] + colpos[n]
+  const uint32_t yend = uint32_t(a.twoB / 2);
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const uint32_t y0 = 8 * (q + 4 * i) + 2 * (l >> 4);   // result rows 2 y0 .. 2 y0 + 3
+    const uint32_t o0 = g0 + s_wrow[y0], o1 = g0 + s_wrow[y0 + 1];
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) {
+      const uint32_t n = 16 * (CB + t) + (l & 15);
+      if (pp_on<MTW, M>(i, t) && n < a.NT) {
+        if (y0 < yend) psi[o0 + uint32_t(cp[t])] = float2{acc[i][t][0], acc[i][t][1]};
+        if (y0 + 1 < yend) psi[o1 + uint32_t(cp[t])] = float2{acc[i][t][2], acc[i][t][3]};
+      }
+    }
+  }
+  if constexpr (LC) {
+    if ((l >> 4) == 0) {
+      float* pf = reinterpret_cast<float*>(psi);
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        const uint32_t r = 16 * (q + 4 * i) + (l & 15);
+        if (r < uint32_t(a.twoB)) pf[2 * uint64_t(g0 + s_wrow[r >> 1] + uint32_t(cl)) + (r & 1)] = part[i];
+      }
+    }
+  }
+}
+
+template <int MTW, int NTILES, int KS, int FILL, bool LEFT, int NBUF>
+__global__ __launch_bounds__(512, 1) void k_fused_pipe(FusedArgs a) {
+  using S = PipeSplit<MTW, NTILES, LEFT>;
+  constexpr int KPAD = 64 * MTW;
+  constexpr int RY = KPAD / 2;
+  static_assert(NTILES % 2 == 0, "column tiles split between the two waves of a SIMD");
+  __shared__ __align__(16) float xbuf[2][NBUF];
+  __shared__ int32_t s_rowpos[2 * RY];
+  __shared__ uint32_t s_wrow[RY];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int64_t* s_hoff = reinterpret_cast<int64_t*>(lds_raw);
+  // wave index through readfirstlane: the compiler sees it uniform, so the per-half branch is
+  // scalar (a wave runs one set of products, not both under an execution mask)
+  const uint32_t tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const uint32_t q = w & 3u;          // row tiles q + 4 i
+  const uint32_t hf = w >> 2;
+  const uint32_t nrow = FILL == 1 ? 2u * RY : uint32_t(RY);
+  for (uint32_t h = tid; h < a.dH; h += 512) s_hoff[h] = a.hoff[h];
+  for (uint32_t y = tid; y < nrow; y += 512) s_rowpos[y] = a.rowpos[y];
+  for (uint32_t y = tid; y < uint32_t(RY); y += 512) s_wrow[y] = a.wrow[y];
+  // LDS tile position of this lane's column in each of its column tiles = its offset in a run
+  int32_t cp[S::NTMAX];
+  {
+    const int cb = hf ? S::CB1 : 0;
+#pragma unroll
+    for (int t = 0; t < S::NTMAX; ++t) cp[t] = a.colpos[16 * std::min(cb + t, NTILES - 1) + (l & 15)];
+  }
+  const int32_t cl = a.colpos[16 * (NTILES - 1)];   // the single column (LEFT)
+  float af[MTW][KS];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int row = 16 * (int(q) + 4 * i) + int(l & 15);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)   // step kk = 2 j + c: real row k = 2 (4 j + (l >> 4)) + c
+      af[i][kk] = a.a32[size_t(row) * KPAD + 2 * (4 * (kk >> 1) + int(l >> 4)) + (kk & 1)];
+  }
+  const uint32_t ntile = blockIdx.x < a.tiles.count ? (a.tiles.count - 1 - blockIdx.x) / gridDim.x + 1 : 0u;
+  __syncthreads();   // tables in LDS
+  if (ntile > 0) pipe_fill_tile<FILL>(a, a.psi, xbuf[0], s_hoff, fm_offset(a.tiles, blockIdx.x), w, l);
+  // tile 0 and the rows of A have arrived (waiting here on every path also tells the compiler that
+  // no load of A is still pending inside the loop)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();   // tile 0 in LDS
+  for (uint32_t p = 0; p < ntile; ++p) {
+    if (hf)
+      pipe_phase<MTW, NTILES, KS, FILL, LEFT, 1>(a, xbuf[p & 1u], xbuf[(p + 1) & 1u], p, ntile, s_hoff, s_rowpos,
+                                                 s_wrow, cp, af, cl, w, l);
+    else
+      pipe_phase<MTW, NTILES, KS, FILL, LEFT, 0>(a, xbuf[p & 1u], xbuf[(p + 1) & 1u], p, ntile, s_hoff, s_rowpos,
+                                                 s_wrow, cp, af, cl, w, l);
+    __syncthreads();   // every wave has read its operands of tile p; tile p + 1 is in LDS
+  }
+}
+
+// whether a block's tile buffers fit a kernel instance with NBUF floats per buffer
+template <int MTW, int NBUF>
+static bool pipe_fits(const FusedArgs& a) {
+  const size_t lds = size_t(2) * NBUF * sizeof(float) + size_t(96 * MTW) * sizeof(int32_t) + size_t(a.dH) * sizeof(int64_t);
+  return pipe_in_floats(a.ES) <= uint32_t(NBUF) && lds <= kLdsBytes;
+}
+
+template <int MTW, int NTILES, int KS, int NBUF, int FILL, bool LEFT>
+static int launch_pipe_fill(const FusedArgs& a, hipStream_t st) {
+  const size_t dyn = size_t(a.dH) * sizeof(int64_t);
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned grid = unsigned(std::min<uint64_t>(a.tiles.count, uint64_t(cus)));
+  auto k = k_fused_pipe<MTW, NTILES, KS, FILL, LEFT, NBUF>;
+  QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(512), dyn, st, a);
+  QD_HIP(hipGetLastError());
+  return QD_OK;
+}
+
+template <int MTW, int NTILES, int KS, int NBUF>
+static int launch_pipe(const FusedArgs& a, hipStream_t st) {
+  if constexpr (NTILES == 6 && KS == 42) {
+    if (a.NT == 16 * (NTILES - 1) + 1) {
+      if (a.fill == 0) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 0, true>(a, st);
+      if (a.fill == 1) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 1, true>(a, st);
+      return launch_pipe_fill<MTW, NTILES, KS, NBUF, 2, true>(a, st);
+    }
+  }
+  if (a.fill == 0) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 0, false>(a, st);
+  if (a.fill == 1) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 1, false>(a, st);
+  return launch_pipe_fill<MTW, NTILES, KS, NBUF, 2, false>(a, st);
 }
 
 template <int MTW, int NTILES, int KS, bool BF>
@@ -724,6 +1032,16 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
     a.rowpos = d.variant <= 3 ? d.tab_rowpos : nullptr;
   }
   const bool bf = mode == QD_MODE_BF16X3_MFMA;
+  // FP32 blocks of 64 < B <= 81: the double-buffered kernel where its two tile buffers (each as
+  // large as the largest fill-1 tile of an 81-wide block over qutrits) fit the LDS of a CU. For
+  // B <= 64 several workgroups per CU of the kernel below measured faster; for B > 81 the
+  // double-buffered kernel's registers spill.
+  if (!bf && a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
+    switch (d.variant) {
+      case 2: if (pipe_fits<3, 13312>(a)) return launch_pipe<3, 6, 42, 13312>(a, s->stream); break;
+      default: break;
+    }
+  }
   if (a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
     switch (d.variant) {
       case 0: return bf ? launch_rows<1, 4, 1, 2, true, 2>(a, s->stream, 4)
@@ -731,7 +1049,7 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
       case 1: return bf ? launch_rows<2, 4, 1, 4, true, 2>(a, s->stream, 3)
                         : launch_rows<2, 4, 1, 32, false, 2>(a, s->stream, 3);
       case 2: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
-                        : launch_rows<3, 6, 2, 41, false, 2>(a, s->stream, 2);
+                        : launch_rows<3, 6, 2, 42, false, 2>(a, s->stream, 2);
       case 3: return bf ? launch_rows<3, 6, 2, 6, true, 2>(a, s->stream, 2)
                         : launch_rows<3, 6, 2, 48, false, 2>(a, s->stream, 2);
       default: break;  // B > 96 keeps the general kernel
@@ -834,6 +1152,7 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
   const int RY = variant_kpad(d->variant) / 2;
   const int NC = 16 * ntiles;
   std::vector<int32_t> rowpos(RY, 0), colpos(NC, 0);   // padding rows and columns alias the first
+  std::vector<uint32_t> wrow(RY, 0);
   {
     // offset inside the run of each window-local digit combination that lies in L, and of each column
     std::vector<int64_t> y_lo(size_t(B), 0);
@@ -850,13 +1169,19 @@ int fused_geometry(const Register& r, FusedBlockDev* d) {
     for (uint64_t h = 0; h < dH; ++h)
       for (int32_t yl : yl_list) {
         const int y = yh[h] + yl;
-        if (y < RY) rowpos[y] = int32_t(h * BL + uint64_t(y_lo[yl]));
+        if (y < RY) {
+          rowpos[y] = int32_t(h * BL + uint64_t(y_lo[yl]));
+          wrow[y] = uint32_t(hoff[h] + y_lo[yl]);
+        }
       }
   }
   QD_HIP(hipMalloc((void**)&d->tab_rowpos, sizeof(int32_t) * RY));
   QD_HIP(hipMalloc((void**)&d->tab_colpos, sizeof(int32_t) * NC));
   QD_HIP(hipMemcpy(d->tab_rowpos, rowpos.data(), sizeof(int32_t) * RY, hipMemcpyHostToDevice));
   QD_HIP(hipMemcpy(d->tab_colpos, colpos.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice));
+  QD_HIP(hipMalloc((void**)&d->tab_wrow, sizeof(uint32_t) * RY));
+  QD_HIP(hipMemcpy(d->tab_wrow, wrow.data(), sizeof(uint32_t) * RY, hipMemcpyHostToDevice));
+  a.wrow = d->tab_wrow;
   a.rowpos = d->variant <= 3 ? d->tab_rowpos : nullptr;
   a.colpos = d->tab_colpos;
   // tile moves in 16-byte units: an odd run length keeps BL + 1 LDS slots per run, the run starting
