@@ -759,6 +759,55 @@ __device__ __forceinline__ void pipe_fill_tile(const FusedArgs& a, float2* __res
   }
 }
 
+// Fill 0 and 1: each lane's 16-byte units (u = 64 w + l + 512 m) as offsets from the tile origin,
+// computed once per launch, so that loading a tile takes two integer operations per unit instead of
+// a division and a table lookup. Unit u of a fill-1 tile starts at origin + rel - parity, where the
+// parity (origin + run offset) & 1 is the origin's parity xor the run offset's (bit m of par).
+constexpr int kPipeUnits = 8;   // units per lane: 512 lanes x 8 units x 2 amplitudes cover every tile
+struct PipeUnits {
+  uint32_t rel[kPipeUnits];
+  uint32_t par;
+};
+
+template <int FILL>
+__device__ __forceinline__ void pipe_units_init(const FusedArgs& a, PipeUnits& pu, uint32_t w, uint32_t l) {
+  static_assert(FILL == 0 || FILL == 1, "16-byte units");
+  const uint32_t units = (FILL == 0 ? a.E : a.ES) >> 1;
+  pu.par = 0;
+#pragma unroll
+  for (int m = 0; m < kPipeUnits; ++m) {
+    const uint32_t u = w * 64 + l + 512u * m;
+    uint32_t rel = 0, par = 0;   // lanes past the end: the tile's first unit (read into the slack)
+    if (u < units) {
+      if constexpr (FILL == 0) {
+        const uint32_t e = 2 * u, h = magic_div(e, a.blm);
+        rel = uint32_t(a.hoff[h]) + (e - h * a.BL);
+      } else {
+        const uint32_t h = magic_div(u, a.upm), k = u - h * a.upr;
+        rel = uint32_t(a.hoff[h]) + 2 * k;
+        par = uint32_t(a.hoff[h]) & 1u;
+      }
+    }
+    pu.rel[m] = rel;
+    pu.par |= par << m;
+  }
+}
+
+template <int FILL>
+__device__ __forceinline__ void pipe_load_units(const FusedArgs& a, float2* __restrict__ psi, float* xs,
+                                                const PipeUnits& pu, uint32_t g0, uint32_t w) {
+  const uint32_t units = (FILL == 0 ? a.E : a.ES) >> 1;
+#pragma unroll
+  for (int m = 0; m < kPipeUnits; ++m) {
+    const uint32_t u0 = w * 64 + 512u * m;
+    if (u0 < units) {
+      uint32_t ga = g0 + pu.rel[m];
+      if constexpr (FILL == 1) ga -= (g0 ^ (pu.par >> m)) & 1u;
+      __builtin_amdgcn_global_load_lds(psi + ga, xs + 4 * u0, 16, 0, kNt);
+    }
+  }
+}
+
 // The products of one wave over one tile: its MTW row tiles of A times its NTH column tiles of X,
 // except the (row tile i, column tile t) pairs whose bit t MTW + i is set in SKIPM. `between` runs
 // after the first operands are read and before the products (the next tile's loads: issued after
@@ -782,35 +831,53 @@ __device__ __forceinline__ void pipe_products(v4f (&acc)[MTW][NTH], const float*
     for (int t = 0; t < NTH; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
   // K in pairs of steps: in steps 2 j and 2 j + 1 lane l takes the real and the imaginary part
   // of amplitude (row y = 4 j + (l >> 4), column n = 16 nt + (l & 15)), one 8-byte LDS read for
-  // two products. The operands of pair j + 1 are loaded before the products of pair j.
-  static_assert(KS % 2 == 0, "K steps in pairs");
+  // two products. The operands of pair j + 1 are loaded before the products of pair j. An odd KS
+  // ends with one single step over real rows k = 4 (KS - 1) + (l >> 4): complex row
+  // 2 (KS - 1) + (l >> 5), part (l >> 4) & 1.
   constexpr int KP = KS / 2;
+  constexpr bool ODD = (KS & 1) != 0;
+  constexpr int NL = KP + (ODD ? 1 : 0);   // operand loads: the pairs, then the single step
   const float2* x2 = reinterpret_cast<const float2*>(xs);
   const int32_t* rpl = rows + (l >> 4);
+  // row of load j (a pair: 4 j + (l >> 4); the single step: 2 (KS - 1) + (l >> 5))
+  auto lrow = [&](int j) -> int32_t { return (ODD && j == KP) ? rows[2 * (KS - 1) + int(l >> 5)] : rpl[4 * j]; };
   float2 b[2][NTH];
-  int32_t rk = rpl[0];
+  int32_t rk = lrow(0);
 #pragma unroll
   for (int t = 0; t < NTH; ++t)
     if (pp_tile<MTW, SKIPM>(t)) b[0][t] = x2[rk + cp[t]];
-  rk = rpl[4];
+  if (NL > 1) rk = lrow(1);
   between();
 #pragma unroll
-  for (int j = 0; j < KP; ++j) {
-    if (j + 1 < KP) {
+  for (int j = 0; j < NL; ++j) {
+    if (j + 1 < NL) {
 #pragma unroll
       for (int t = 0; t < NTH; ++t)
         if (pp_tile<MTW, SKIPM>(t)) b[(j + 1) & 1][t] = x2[rk + cp[t]];
-      if (j + 2 < KP) rk = rpl[4 * (j + 2)];
+      if (j + 2 < NL) rk = lrow(j + 2);
     }
     __builtin_amdgcn_sched_barrier(0);
+    if (!(ODD && j == KP)) {
 #pragma unroll
-    for (int t = 0; t < NTH; ++t)
+      for (int t = 0; t < NTH; ++t)
 #pragma unroll
-      for (int i = 0; i < MTW; ++i)
-        if (pp_on<MTW, SKIPM>(i, t)) {
-          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j], b[j & 1][t].x, acc[i][t], 0, 0, 0);
-          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j + 1], b[j & 1][t].y, acc[i][t], 0, 0, 0);
-        }
+        for (int i = 0; i < MTW; ++i)
+          if (pp_on<MTW, SKIPM>(i, t)) {
+            acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j], b[j & 1][t].x, acc[i][t], 0, 0, 0);
+            acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][2 * j + 1], b[j & 1][t].y, acc[i][t], 0, 0, 0);
+          }
+    } else {
+      const bool im = ((l >> 4) & 1u) != 0;   // this lane's part of the amplitude
+#pragma unroll
+      for (int t = 0; t < NTH; ++t) {
+        const float2 v = b[j & 1][t];   // (selecting from a copy keeps b in registers)
+        const float bv = im ? v.y : v.x;
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+          if (pp_on<MTW, SKIPM>(i, t))
+            acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][KS - 1], bv, acc[i][t], 0, 0, 0);
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -838,7 +905,8 @@ __device__ __forceinline__ void pipe_phase(const FusedArgs& a, float* __restrict
                                            uint32_t p, uint32_t ntile, const int64_t* s_hoff,
                                            const int32_t* s_rowpos, const uint32_t* s_wrow,
                                            const int32_t (&cpa)[PipeSplit<MTW, NTILES, LEFT>::NTMAX],
-                                           const float (&af)[MTW][KS], int32_t cl, uint32_t w, uint32_t l) {
+                                           const float (&af)[MTW][KS], int32_t cl, const PipeUnits& pu,
+                                           uint32_t w, uint32_t l) {
   using S = PipeSplit<MTW, NTILES, LEFT>;
   constexpr int RY = 32 * MTW;
   constexpr int NTH = H ? S::NT1 : S::NT0;
@@ -855,8 +923,11 @@ __device__ __forceinline__ void pipe_phase(const FusedArgs& a, float* __restrict
 
   v4f acc[MTW][NTH];
   pipe_products<MTW, NTH, KS, M>(acc, xs, rows, cp, af, l, [&] {
-    if (p + 1 < ntile)
-      pipe_fill_tile<FILL>(a, psi, xn, s_hoff, fm_offset(a.tiles, blockIdx.x + (p + 1) * gridDim.x), w, l);
+    if (p + 1 < ntile) {
+      const int64_t gn = fm_offset(a.tiles, blockIdx.x + (p + 1) * gridDim.x);
+      if constexpr (FILL == 2) pipe_fill_tile<FILL>(a, psi, xn, s_hoff, gn, w, l);
+      else pipe_load_units<FILL>(a, psi, xn, pu, uint32_t(gn), w);
+    }
   });
   float part[MTW];
   if constexpr (LC) {
@@ -870,6 +941,12 @@ __device__ __forceinline__ void pipe_phase(const FusedArgs& a, float* __restrict
       const float2 x = x2[rows[4 * j + int(l >> 4)] + cl];
 #pragma unroll
       for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][2 * j + 1], x.y, fmaf(af[i][2 * j], x.x, part[i]));
+    }
+    if constexpr ((KS & 1) != 0) {   // the single last step: complex row 2 (KS - 1) + (l >> 5)
+      const float2 x = x2[rows[2 * (KS - 1) + int(l >> 5)] + cl];
+      const float xv = ((l >> 4) & 1u) ? x.y : x.x;
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) part[i] = fmaf(af[i][KS - 1], xv, part[i]);
     }
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
@@ -938,12 +1015,21 @@ __global__ __launch_bounds__(512, 1) void k_fused_pipe(FusedArgs a) {
   for (int i = 0; i < MTW; ++i) {
     const int row = 16 * (int(q) + 4 * i) + int(l & 15);
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk)   // step kk = 2 j + c: real row k = 2 (4 j + (l >> 4)) + c
-      af[i][kk] = a.a32[size_t(row) * KPAD + 2 * (4 * (kk >> 1) + int(l >> 4)) + (kk & 1)];
+    for (int kk = 0; kk < KS; ++kk) {
+      // step kk = 2 j + c of a pair: real row k = 2 (4 j + (l >> 4)) + c; an odd last step: 4 kk + (l >> 4)
+      const int k = ((KS & 1) && kk == KS - 1) ? 4 * kk + int(l >> 4) : 2 * (4 * (kk >> 1) + int(l >> 4)) + (kk & 1);
+      af[i][kk] = a.a32[size_t(row) * KPAD + k];
+    }
   }
+  PipeUnits pu;
+  if constexpr (FILL != 2) pipe_units_init<FILL>(a, pu, w, l);
   const uint32_t ntile = blockIdx.x < a.tiles.count ? (a.tiles.count - 1 - blockIdx.x) / gridDim.x + 1 : 0u;
   __syncthreads();   // tables in LDS
-  if (ntile > 0) pipe_fill_tile<FILL>(a, a.psi, xbuf[0], s_hoff, fm_offset(a.tiles, blockIdx.x), w, l);
+  if (ntile > 0) {
+    const int64_t g0 = fm_offset(a.tiles, blockIdx.x);
+    if constexpr (FILL == 2) pipe_fill_tile<FILL>(a, a.psi, xbuf[0], s_hoff, g0, w, l);
+    else pipe_load_units<FILL>(a, a.psi, xbuf[0], pu, uint32_t(g0), w);
+  }
   // tile 0 and the rows of A have arrived (waiting here on every path also tells the compiler that
   // no load of A is still pending inside the loop)
   __builtin_amdgcn_s_waitcnt(0);
@@ -951,10 +1037,10 @@ __global__ __launch_bounds__(512, 1) void k_fused_pipe(FusedArgs a) {
   for (uint32_t p = 0; p < ntile; ++p) {
     if (hf)
       pipe_phase<MTW, NTILES, KS, FILL, LEFT, 1>(a, xbuf[p & 1u], xbuf[(p + 1) & 1u], p, ntile, s_hoff, s_rowpos,
-                                                 s_wrow, cp, af, cl, w, l);
+                                                 s_wrow, cp, af, cl, pu, w, l);
     else
       pipe_phase<MTW, NTILES, KS, FILL, LEFT, 0>(a, xbuf[p & 1u], xbuf[(p + 1) & 1u], p, ntile, s_hoff, s_rowpos,
-                                                 s_wrow, cp, af, cl, w, l);
+                                                 s_wrow, cp, af, cl, pu, w, l);
     __syncthreads();   // every wave has read its operands of tile p; tile p + 1 is in LDS
   }
 }
@@ -963,7 +1049,8 @@ __global__ __launch_bounds__(512, 1) void k_fused_pipe(FusedArgs a) {
 template <int MTW, int NBUF>
 static bool pipe_fits(const FusedArgs& a) {
   const size_t lds = size_t(2) * NBUF * sizeof(float) + size_t(96 * MTW) * sizeof(int32_t) + size_t(a.dH) * sizeof(int64_t);
-  return pipe_in_floats(a.ES) <= uint32_t(NBUF) && lds <= kLdsBytes;
+  const bool units_fit = a.fill == 2 || ((a.fill == 0 ? a.E : a.ES) >> 1) <= 512u * kPipeUnits;
+  return pipe_in_floats(a.ES) <= uint32_t(NBUF) && lds <= kLdsBytes && units_fit;
 }
 
 template <int MTW, int NTILES, int KS, int NBUF, int FILL, bool LEFT>
@@ -982,7 +1069,7 @@ static int launch_pipe_fill(const FusedArgs& a, hipStream_t st) {
 
 template <int MTW, int NTILES, int KS, int NBUF>
 static int launch_pipe(const FusedArgs& a, hipStream_t st) {
-  if constexpr (NTILES == 6 && KS == 42) {
+  if constexpr (NTILES == 6 && KS == 41) {
     if (a.NT == 16 * (NTILES - 1) + 1) {
       if (a.fill == 0) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 0, true>(a, st);
       if (a.fill == 1) return launch_pipe_fill<MTW, NTILES, KS, NBUF, 1, true>(a, st);
@@ -1038,7 +1125,7 @@ int launch_fused_block(qd_state* s, const qd_fused* f, int b, int mode) {
   // double-buffered kernel's registers spill.
   if (!bf && a.rowpos && a.NT <= uint32_t(16 * variant_ntiles(d.variant))) {
     switch (d.variant) {
-      case 2: if (pipe_fits<3, 13312>(a)) return launch_pipe<3, 6, 42, 13312>(a, s->stream); break;
+      case 2: if (pipe_fits<3, 13312>(a)) return launch_pipe<3, 6, 41, 13312>(a, s->stream); break;
       default: break;
     }
   }
