@@ -90,8 +90,10 @@ const char* qd_last_error(void);
 /* Name of the kernel instance that the calling thread's last qd_apply_gate / qd_apply_gate_ex
  * launched, e.g. "k_slices_direct<double, 2, DenseOp<double, 2>, 1, plain>" (template arguments:
  * precision, slice size d_T after any control folded into the targets, gate operation, slices per
- * thread and the control mode plain / pred / edge); "" when that call launched nothing. Static
- * thread-local storage, for profiling labels; it changes no state. */
+ * thread and the control mode plain / pred / edge), or that the last block of its last
+ * qd_apply_fused launched (e.g. "k_fused_pipe<3, 6, 41, 1, true, 13312>", the template arguments
+ * as rocprofv3 prints them); "" when that call launched nothing. Static thread-local storage, for
+ * profiling labels; it changes no state. */
 const char* qd_last_kernel(void);
 
 /* Gate kernel launches made on a state since it was created: one per qd_apply_gate that moved

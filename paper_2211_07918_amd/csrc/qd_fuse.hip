@@ -293,6 +293,7 @@ int qd_fused_download_block(const qd_fused* f, int32_t b, double* out) {
 int qd_apply_fused(qd_state* s, const qd_fused* f, int32_t mode_flags) {
   if (!s || !f) return fail(QD_EINVAL, "null argument");
   if (mode_flags & ~int32_t(0xFF | QD_FUSED_RENORMALIZE)) return fail(QD_EINVAL, "unknown mode flag");
+  set_last_kernel("");
   const int32_t mode = mode_flags & 0xFF;
   const bool renorm = (mode_flags & QD_FUSED_RENORMALIZE) != 0;
   if (s->reg.n != f->reg.n) return fail(QD_EDIM, "register differs from the fused circuit's");

@@ -1237,5 +1237,6 @@ int launch_gate(qd_state* s, const GatePlan& p) {
 }
 
 const char* last_kernel() { return g_last_kernel; }
+void set_last_kernel(const char* name) { g_last_kernel = name; }
 
 }  // namespace qd

@@ -186,7 +186,8 @@ int sparse_apply_gates(qd_sparse* s, const SparseGate* gates, size_t count, uint
 
 // Launchers (qd_gates.hip)
 int launch_gate(qd_state* s, const GatePlan& p);
-const char* last_kernel();   // kernel instance of the calling thread's last launch_gate ("" if none)
+const char* last_kernel();   // kernel instance of the calling thread's last gate or fused-block launch
+void set_last_kernel(const char* name);   // (static storage; "" for none)
 int launch_fill_basis(qd_state* s, int64_t index);
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 
 #include "qd_fused.h"
@@ -653,6 +654,30 @@ __global__ __launch_bounds__(256, WPE) void k_fused_rows(FusedArgs a) {
   }
 }
 
+// kernel instance names for qd_last_kernel, formatted once per instance as rocprofv3 prints them
+template <int MTW, int NTILES, int NH, int KS, bool BF, int WPE, int FILL, bool LEFT>
+static const char* rows_label() {
+  static thread_local char buf[96] = {0};
+  if (!buf[0])
+    std::snprintf(buf, sizeof(buf), "k_fused_rows<%d, %d, %d, %d, %s, %d, %d, %s>", MTW, NTILES, NH, KS,
+                  BF ? "true" : "false", WPE, FILL, LEFT ? "true" : "false");
+  return buf;
+}
+template <int MTW, int NTILES, int KS, int FILL, bool LEFT, int NBUF>
+static const char* pipe_label() {
+  static thread_local char buf[96] = {0};
+  if (!buf[0])
+    std::snprintf(buf, sizeof(buf), "k_fused_pipe<%d, %d, %d, %d, %s, %d>", MTW, NTILES, KS, FILL,
+                  LEFT ? "true" : "false", NBUF);
+  return buf;
+}
+template <int MTW, int NTILES, int KS, bool BF>
+static const char* general_label() {
+  static thread_local char buf[96] = {0};
+  if (!buf[0]) std::snprintf(buf, sizeof(buf), "k_fused<%d, %d, %d, %s>", MTW, NTILES, KS, BF ? "true" : "false");
+  return buf;
+}
+
 static size_t rows_lds(const FusedArgs& a, int ry) {
   return size_t(rows_buf_floats(a.ES)) * sizeof(float) + size_t(2 * ry) * sizeof(int32_t) +
          size_t(a.dH) * sizeof(int64_t);
@@ -671,6 +696,7 @@ static int launch_rows_fill(const FusedArgs& a, hipStream_t st, int per_cu) {
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
   QD_HIP(hipGetLastError());
+  set_last_kernel(rows_label<MTW, NTILES, NH, KS, BF, WPE, FILL, LEFT>());
   return QD_OK;
 }
 
@@ -1064,6 +1090,7 @@ static int launch_pipe_fill(const FusedArgs& a, hipStream_t st) {
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(512), dyn, st, a);
   QD_HIP(hipGetLastError());
+  set_last_kernel(pipe_label<MTW, NTILES, KS, FILL, LEFT, NBUF>());
   return QD_OK;
 }
 
@@ -1093,6 +1120,7 @@ static int launch_one(const FusedArgs& a, hipStream_t st, int per_cu) {
   QD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
   QD_HIP(hipGetLastError());
+  set_last_kernel(general_label<MTW, NTILES, KS, BF>());
   return QD_OK;
 }
 

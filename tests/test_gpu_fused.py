@@ -276,3 +276,63 @@ def test_odd_runs_on_an_exact_size_buffer(stream, mode):
         Q.qd_fused_free(f)
     assert np.array_equal(own, wrapped)
     assert precision(O.run_circuit(circ), own)[2] <= 1e-6
+
+
+# One block per circuit (a single Haar gate on the window), shaped to reach every matrix-core
+# kernel instance: (dims, window, FP32 instance, BF16x3 instance, exact-size caller buffer)
+SHAPES = [
+    # 81-wide blocks on the double-buffered FP32 kernel
+    ((3, 3, 3, 3, 2, 2), (0, 1, 2, 3), "k_fused_pipe<3, 6, 41, 0, false, 13312>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 0, false>", False),          # runs of even length (324)
+    ((3,) * 6, (0, 1, 2, 3), "k_fused_pipe<3, 6, 41, 1, false, 13312>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 1, false>", False),          # odd runs, 9 columns
+    ((3,) * 9, (0, 1, 2, 3), "k_fused_pipe<3, 6, 41, 1, true, 13312>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 1, false>", False),          # 81 runs of 81 above the window's rows
+    ((3,) * 8, (4, 5, 6, 7), "k_fused_pipe<3, 6, 41, 1, true, 13312>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 1, false>", False),          # the window inside one run
+    ((3,) * 9, (0, 1, 2, 3), "k_fused_pipe<3, 6, 41, 2, true, 13312>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 2, false>", True),           # 4-byte units
+    # the multi-workgroup kernel for B <= 64 and 81 < B <= 96, the general one above 96
+    ((4, 4, 4, 2, 2), (0, 1, 2), "k_fused_rows<2, 4, 1, 32, false, 2, 0, false>",
+     "k_fused_rows<2, 4, 1, 4, true, 2, 0, false>", False),
+    ((4, 4, 4, 3, 3, 3, 3), (0, 1, 2), "k_fused_rows<2, 4, 1, 32, false, 2, 1, false>",
+     "k_fused_rows<2, 4, 1, 4, true, 2, 1, false>", False),
+    ((2, 2, 2, 2, 2, 3, 3, 3, 3), (0, 1, 2, 3, 4), "k_fused_rows<1, 4, 1, 16, false, 2, 1, false>",
+     "k_fused_rows<1, 4, 1, 2, true, 2, 1, false>", False),
+    ((2, 4, 4, 3, 3, 2), (0, 1, 2, 3), "k_fused_rows<3, 6, 2, 48, false, 2, 0, false>",
+     "k_fused_rows<3, 6, 2, 6, true, 2, 0, false>", False),
+    ((2,) * 7 + (3,), tuple(range(7)), "k_fused<4, 4, 64, false>", "k_fused<4, 4, 8, true>", False),
+]
+
+
+@pytest.mark.parametrize("dims,window,k32,kbf,exact", SHAPES)
+def test_kernel_instances_by_block_shape(stream, dims, window, k32, kbf, exact):
+    """Each block shape reaches the kernel instance it is meant for (qd_last_kernel after the run),
+    and both matrix-core modes meet the precision gate against the oracle there."""
+    import torch
+    rng = C.seeded_rng(sum(dims) * 31 + len(window))
+    dT = int(np.prod([dims[q] for q in window]))
+    D = int(np.prod(dims))
+    circ = C.Circuit(tuple(dims), [C.Gate("U", tuple(window), U=C.haar_unitary(dT, rng))],
+                     init_amps=C.random_basis_superposition(D, min(D, 64), rng))
+    f = fuse(circ, 128, stream)
+    try:
+        assert Q.qd_fused_count(f) == 1
+        assert Q.qd_fused_block_info(f, 0)["B"] == dT
+        ref = O.run_circuit(circ)
+        for mode, want in ((Q.QD_MODE_FP32_MFMA, k32), (Q.QD_MODE_BF16X3_MFMA | Q.QD_FUSED_RENORMALIZE, kbf)):
+            if exact:   # a caller's buffer of exactly D amplitudes: no spare read past the last one
+                buf = torch.zeros(D, dtype=torch.complex64, device="cuda")
+                s = Q.qd_state_wrap(circ.dims, Q.QD_C64, buf.data_ptr(), D * 8, stream)
+            else:
+                s = Q.qd_state_init(circ.dims, Q.QD_C64, stream)
+            try:
+                Q.qd_state_upload(s, circ.init_amps)
+                Q.qd_apply_fused(s, f, mode)
+                assert Q.qd_last_kernel() == want, (dims, window, mode, Q.qd_last_kernel())
+                psi = Q.qd_state_download(s)
+            finally:
+                Q.qd_state_free(s)
+            assert_gate(ref, psi, (dims, window, want))
+    finally:
+        Q.qd_fused_free(f)
