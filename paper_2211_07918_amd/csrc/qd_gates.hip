@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "qd_internal.h"
@@ -143,7 +144,13 @@ struct DirectArgs {
   OP op;
   // kDirectPred: the low-stride controls are free digits of sm (singleton groups whose lmul weights
   // give their local index); a slice is mixed when that index equals vloc, else written unchanged.
+  // Lines holding no amplitude where those controls all have their values are left untouched when
+  // lper > 1: line L holds one iff bit (L mod lper) of lmask is set (the pattern of the low control
+  // digits repeats every lper lines).
   uint32_t vloc;
+  uint32_t lper;
+  Magic32 lpm;
+  uint64_t lmask;
   // kDirectEdge (every target above the lowest control): sm enumerates the active slices, grouped
   // into blocks of nA = blen consecutive indices (the blen contiguous amplitudes where the lowest
   // control holds its value, all higher digits fixed, each a slice base). Each block gets W lanes,
@@ -220,6 +227,15 @@ __global__ __launch_bounds__(256) void k_slices_direct(DirectArgs<R, DT, OP> a) 
       uint32_t loc;
       pos = sm_offset_loc(a.sm, uint32_t(i), &loc);
       act = loc == a.vloc;
+      if (!act && a.lper > 1) {
+        valid = 0;
+#pragma unroll
+        for (int y = 0; y < DT; ++y) {
+          const uint32_t L = uint32_t((pos + a.toff[y]) >> kLineShift<R>);
+          if ((a.lmask >> (L - magic_div(L, a.lpm) * a.lper)) & 1u) valid |= 1u << y;
+        }
+        if (!valid) return;
+      }
     } else {
       // the block's lanes walk its lines in order: lane j takes amplitude L0 + j, L0 the start of
       // the line holding the block's first amplitude, so every instruction writes whole lines
@@ -751,6 +767,38 @@ static int check_launch(const char* what) {
   return QD_OK;
 }
 
+// Which lines of `line` amplitudes hold an amplitude where every control of stride below one line
+// has its value. Those control digits repeat with period P = lcm(s_c d_c), so the lines repeat with
+// period lcm(P, line) / line; for a period of 2..64 lines, *per is set to it and bit j of *mask
+// tells whether line j of a period holds such an amplitude (else *per = 1: treat every line so).
+static void line_pattern(const Register& r, const GatePlan& p, int64_t line, uint32_t* per, uint64_t* mask) {
+  *per = 1;
+  *mask = 1;
+  uint64_t P = 1;
+  for (int j = 0; j < p.m; ++j) {
+    const int c = p.controls[j];
+    if (r.strides[c] < line) P = std::lcm(P, uint64_t(r.strides[c]) * uint64_t(r.dims[c]));
+  }
+  const uint64_t per_lines = std::lcm(P, uint64_t(line)) / uint64_t(line);
+  if (per_lines < 2 || per_lines > 64) return;
+  uint64_t m = 0;
+  for (uint64_t L = 0; L < per_lines; ++L)
+    for (uint64_t i = L * uint64_t(line); i < (L + 1) * uint64_t(line); ++i) {
+      bool all = true;
+      for (int j = 0; j < p.m && all; ++j) {
+        const int c = p.controls[j];
+        if (r.strides[c] < line) all = (i / uint64_t(r.strides[c])) % uint64_t(r.dims[c]) == uint64_t(p.cvals[j]);
+      }
+      if (all) {
+        m |= uint64_t(1) << L;
+        break;
+      }
+    }
+  if (m == (per_lines == 64 ? ~uint64_t(0) : (uint64_t(1) << per_lines) - 1)) return;   // every line
+  *per = uint32_t(per_lines);
+  *mask = m;
+}
+
 // target offsets: y in mixed radix over the targets in listed order, t_0 most significant
 static void target_offsets(const Register& r, const GatePlan& p, int64_t* toff) {
   for (int y = 0; y < p.dT; ++y) {
@@ -992,6 +1040,8 @@ static int launch_slices(qd_state* s, const GatePlan& p, const OP& op) {
   if (a.sm.count == 0) return QD_OK;
   const int bs = ent.block;
   if (nlow) {
+    line_pattern(r, p, line, &a.lper, &a.lmask);
+    if (a.lper > 1) a.lpm = make_magic32(a.lper);
     hipLaunchKernelGGL((k_slices_direct<R, DT, OP, 1, kDirectPred>), dim3(grid_for(a.sm.count, uint64_t(bs))), dim3(bs), 0,
                        s->stream, a);
     g_last_kernel = label<kKnDirect, R, DT, OP, 1, kDirectPred>();

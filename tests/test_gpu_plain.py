@@ -521,8 +521,10 @@ def test_tiled_kernel_walks_tiles_beyond_the_grid_cap(stream, prec):
 @pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
 def test_direct_controls_whole_lines(stream, prec):
     """Controlled gates on the slice-per-thread kernel where the control's active runs do not
-    cover whole 128-byte lines: controls of stride below one line (tested per slice, every slice
-    written), and a lowest control whose stride is not a whole number of lines (edge lanes rewrite
+    cover whole 128-byte lines: controls of stride below one line (tested per slice, every slice of a
+    line holding an active amplitude written, lines with none left untouched: the stride-6 qutrit
+    controls leave a third of the lines inactive), and a lowest control whose stride is not a whole
+    number of lines (edge lanes rewrite
     the rest of the partly active lines): targets above and below the control, two controls, the
     last line of a register whose size is no multiple of a line, dense and monomial U, each
     against the oracle."""
@@ -533,7 +535,7 @@ def test_direct_controls_whole_lines(stream, prec):
             ((0,), (8,), (2,)), ((2,), (7,), (1,)), ((3,), (6, 8), (1, 0)), ((1,), (6, 4), (2, 1)),
             ((5,), (7,), (1,)), ((0,), (5,), (2,)), ((2,), (4,), (1,)), ((5,), (3,), (0,)),
             ((1, 4), (3,), (1,)), ((0,), (5, 3), (1, 2)), ((0,), (2,), (3,)), ((0,), (1,), (1,)),
-            ((4, 1), (5,), (4,)),
+            ((4, 1), (5,), (4,)), ((0,), (6,), (2,)), ((2,), (6, 7), (0, 1)),
         ],
         # strides 135, 45, 9, 3, 1 (D = 405: the last line is partial)
         (3, 3, 5, 3, 3): [((0,), (2,), (4,)), ((1,), (2,), (0,)), ((0,), (1,), (2,)), ((0, 1), (2,), (3,))],
