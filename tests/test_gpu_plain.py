@@ -446,6 +446,8 @@ def test_tiled_controls_inside_the_suffix(stream, prec, tile_elems):
         ((10,), (7, 6, 5), (0, 1, 1)),       # three: the third stays above the tile
         ((10, 4), (7,), (1,)),               # a high target (two runs per tile) and a control inside
         ((8,), (4, 2), (1, 0)),              # controls of strides 216 and 1728
+        ((10,), (8,), (2,)),                 # stride 6, inside a line
+        ((9,), (8, 7), (0, 1)),              # stride 6 inside the tile and stride 18 left out
     ]
     dims9 = (2, 3, 2, 4, 2, 9, 3)                     # a 9-level target over a qutrit of stride 1
     D9 = O.register_size(dims9)
