@@ -131,7 +131,9 @@ int qd_gate_class(const double* U, int32_t dT);
 
 /* Kernel family qd_apply_gate would launch for this gate on a state of register dims and
  * precision prec, written to *route_out (host only, no device work):
- *   QD_ROUTE_DIRECT  one slice per thread (every target stride >= the run threshold);
+ *   QD_ROUTE_DIRECT  one slice per thread (every target stride >= the run threshold, or every
+ *                    target stride >= one 128-byte line with controls inside a line that leave
+ *                    lines without a matching amplitude: those lines are skipped);
  *   QD_ROUTE_TILED   slices staged in LDS (a target with a small stride);
  *   QD_ROUTE_DIAG    elementwise phases (diagonal U);
  *   QD_ROUTE_GEMM    dense 10 <= d_T <= 64 (and other monomials in that range): per tile of

@@ -844,6 +844,16 @@ bool tile_geometry(const Register& r, const GatePlan& p, int prec, TileGeom* g) 
     }
   const TuneEntry e = entry_for(prec, min_stride);
   if (!e.tiled) return false;
+  {
+    // Controls inside a line that leave whole lines without a matching amplitude: the predicated
+    // direct kernel skips those lines and the tile kernel would move them. With every target at
+    // least a line apart the direct kernel's lanes still take whole lines, so it runs such gates.
+    const int64_t line = prec == QD_C128 ? 8 : 16;
+    uint32_t per = 1;
+    uint64_t mask = 1;
+    if (min_stride >= line) line_pattern(r, p, line, &per, &mask);
+    if (per > 1) return false;
+  }
   int low_idx = min_t;
   for (int j = 0; j < p.k; ++j)
     if (r.strides[p.targets[j]] < tp.run_min) low_idx = std::min(low_idx, int(p.targets[j]));

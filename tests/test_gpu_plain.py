@@ -575,3 +575,46 @@ def test_direct_controls_whole_lines(stream, prec):
                 x0 = psi0.astype(out.dtype)
                 assert np.array_equal(out[~act], x0[~act]), (dims, t, c, kind)
     assert seen == {"pred", "edge", "aligned"}
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_inline_controls_take_the_direct_route(stream, prec):
+    """With the run threshold raised so that a target of stride 18 would be staged in LDS, a gate
+    whose control of stride 6 (a qutrit, inside a line) leaves lines without a matching amplitude
+    still runs on the direct kernel, which skips those lines; a control of stride 1 (every line
+    matches somewhere) keeps the tile route, and so does every case in complex64, whose 16-amplitude
+    lines all hold a matching amplitude here. Each against the oracle."""
+    dims = (3, 2, 4, 3, 2, 5, 3, 2, 3)                # strides 4320, 2160, 540, 180, 90, 18, 6, 3, 1
+    rng = C.seeded_rng(101)
+    D = O.register_size(dims)
+    psi0 = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    line = 8 if prec == Q.QD_C128 else 16
+    st = O.strides(dims)
+    idx = np.arange(D)
+    Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 64)
+    try:
+        seen = set()
+        for t, c, v in (((5,), (6,), (2,)), ((5,), (6, 7), (0, 1)), ((5,), (8,), (1,))):
+            act = np.ones(D, bool)
+            for q, val in zip(c, v):
+                act &= (idx // st[q]) % dims[q] == val
+            full = D - D % line
+            skips = not act[:full].reshape(-1, line).any(axis=1).all()
+            route = Q.QD_ROUTE_DIRECT if skips else Q.QD_ROUTE_TILED
+            seen.add(route)
+            U = C.haar_unitary(5, rng)
+            assert Q.qd_gate_route(dims, prec, t, c, v, U) == route, (t, c, prec)
+            s = Q.qd_state_init(dims, prec, stream)
+            try:
+                Q.qd_state_upload(s, psi0)
+                Q.qd_apply_gate(s, t, c, v, U)
+                out = Q.qd_state_download(s)
+            finally:
+                Q.qd_state_free(s)
+            ref = O.apply_gate(psi0, dims, t, c, v, U)
+            tol = 1e-12 if prec == Q.QD_C128 else c64_tol(1, 5)
+            assert max_abs(out, ref) <= tol, (t, c, prec)
+        assert Q.QD_ROUTE_TILED in seen and (prec == Q.QD_C64 or Q.QD_ROUTE_DIRECT in seen)
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)
