@@ -146,6 +146,68 @@ def test_routes():
     assert Q.qd_tune_get(Q.QD_TUNE_RUN_MIN) == 16
 
 
+def _skips_lines(dims, controls, values, line):
+    """Whether some 128-byte line (`line` amplitudes) holds no amplitude where every control of
+    stride below a line has its value, judged over one period of those controls' digit pattern
+    (at most 64 lines, as the library looks; a longer period counts as no skip)."""
+    st = O.strides(dims)
+    low = [(st[c], dims[c], v) for c, v in zip(controls, values) if st[c] < line]
+    P = 1
+    for s, d, _ in low:
+        P = np.lcm(P, s * d)
+    per = int(np.lcm(P, line) // line)
+    if per < 2 or per > 64:
+        return False
+    i = np.arange(per * line)
+    match = np.ones(i.size, bool)
+    for s, d, v in low:
+        match &= (i // s) % d == v
+    return not match.reshape(per, line).any(axis=1).all()
+
+
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_inline_control_route_rule(prec):
+    """Controls inside a line (stride below one 128-byte line) leave the tile geometry as it is
+    without them, so such a gate takes the route of its uncontrolled form, except that it moves to
+    the direct kernel (which skips lines) when its controls leave some line without a matching
+    amplitude and every target stride is at least one line. Run threshold raised to 1024 so that
+    the tile route is the rule; seeded registers of qubits to ququints, one or two targets."""
+    line = 8 if prec == Q.QD_C128 else 16
+    rng = np.random.default_rng(2211)
+    Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 1024)
+    try:
+        seen = {}
+        for _ in range(600):
+            n = int(rng.integers(6, 10))
+            dims = [int(x) for x in rng.integers(2, 6, size=n)]
+            st = O.strides(dims)
+            inl = [q for q in range(n) if st[q] < line]
+            m = int(rng.integers(1, 3))
+            if len(inl) < m:
+                continue
+            c = [int(x) for x in rng.permutation(inl)[:m]]
+            rest = [q for q in range(n) if q not in c and st[q] < 1024]
+            k = int(rng.integers(1, 3))
+            if len(rest) < k:
+                continue
+            t = [int(x) for x in rng.permutation(rest)[:k]]
+            v = [int(rng.integers(0, dims[q])) for q in c]
+            dT = int(np.prod([dims[q] for q in t]))
+            U = C.haar_unitary(dT, rng)
+            plain = Q.qd_gate_route(dims, prec, t, [], [], U)
+            got = Q.qd_gate_route(dims, prec, t, c, v, U)
+            if plain not in (Q.QD_ROUTE_DIRECT, Q.QD_ROUTE_TILED):
+                continue   # d_T beyond the slice kernels: GEMM or generic
+            skip = min(st[q] for q in t) >= line and _skips_lines(dims, c, v, line)
+            want = Q.QD_ROUTE_DIRECT if (plain == Q.QD_ROUTE_TILED and skip) else plain
+            assert got == want, (dims, t, c, v, prec)
+            key = "moved" if plain != want else ("tiled" if want == Q.QD_ROUTE_TILED else "direct")
+            seen[key] = seen.get(key, 0) + 1
+        assert seen.get("tiled", 0) >= 50 and seen.get("moved", 0) >= 50, seen
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)
+
+
 def test_tune_parameters():
     for p, v in ((Q.QD_TUNE_DIRECT_BLOCK, 128), (Q.QD_TUNE_DIRECT_SPT, 1), (Q.QD_TUNE_TILE_ELEMS, 1024),
                  (Q.QD_TUNE_BATCH_GRID, 16)):
