@@ -159,21 +159,30 @@ def bench_plain(args, Q, torch, circ):
     }
 
 
+def code_digest(text: str) -> str:
+    """sha256 of C++/HIP source with its comments and whitespace removed: a counter summary stays
+    valid across edits that only touch comments or layout."""
+    import hashlib
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` (its qd_last_kernel label) from the committed
     hardware-counter summary, if that summary was taken on the current source of the gate kernels
     (else None), with a note of where the figure comes from."""
     import glob
-    import hashlib
     src = os.path.join(ROOT, "paper_2211_07918_amd", "csrc", "qd_gates.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = code_digest(open(src).read())
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
         fields = {}
         for line in open(path):
             if ": " in line and not line.startswith(("#", "`", "|")):
                 k, v = line.split(": ", 1)
                 fields[k.strip()] = v.strip()
-        if fields.get("source_sha256") == digest and fields.get("label", "").replace(" ", "") == kernel.replace(" ", ""):
+        if fields.get("source_code_sha256") == digest and fields.get("label", "").replace(" ", "") == kernel.replace(" ", ""):
             return (float(fields["traffic_bytes_per_launch"]),
                     f"rocprofv3 FETCH_SIZE + WRITE_SIZE counters from the committed summary "
                     f"{os.path.relpath(path, ROOT)} (taken on the current gate-kernel source), not measured in this run")

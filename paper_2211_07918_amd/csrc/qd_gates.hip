@@ -6,7 +6,8 @@
 // vector, at O(D d_T) cost.
 //
 // Kernel families (each HBM-bound: at most 8 d_T flops per 2 x 16 bytes moved):
-//   k_slices_direct  one slice per thread. Used when every target has a stride >= run_min, so the
+//   k_slices_direct  one slice per thread. Used when every target has a stride >= run_min (or at
+//                    least one line, for controls inside a line that leave lines inactive), so the
 //                    lanes of a wavefront take consecutive low digits and each load instruction
 //                    reads one contiguous run.
 //   k_slices_tiled   a low-stride target: the workgroup stages a tile of whole slices in LDS with
@@ -128,11 +129,12 @@ __device__ __forceinline__ void mix_store(C* p, int64_t base, const int64_t*, co
 }
 
 // ------------------------------------------------------------------------------------------ direct
-// Controls whose stride is below one 128-byte line leave every line partly active, and controls of
+// Controls whose stride is below one 128-byte line leave lines partly active, and controls of
 // larger stride that is not a whole number of lines leave the lines at both ends of every active
 // run partly active. HBM is written in whole lines here (a partial line costs a read-modify-write),
 // so both cases are applied with whole-line writes: amplitudes of inactive slices that share a line
-// with active ones are read and written back unchanged.
+// with active ones are read and written back unchanged, and lines with no active amplitude at all
+// are not touched.
 enum { kDirectPlain = 0, kDirectPred = 1, kDirectEdge = 2 };
 
 template <typename R, int DT, typename OP>
