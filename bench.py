@@ -62,6 +62,42 @@ def parse():
     return ap.parse_args()
 
 
+class TimingEvent:
+    """A HIP timing event created with hipEventDisableSystemFence on the HIP runtime torch loaded:
+    recording it skips the system-scope cache writeback and invalidation that a default event
+    performs (the event only times work; nothing waits on it). Same interface as the part of
+    torch.cuda.Event used here."""
+    _hip = None
+    FLAG = 0x20000000   # hipEventDisableSystemFence
+
+    def __init__(self, torch, stream):
+        import ctypes
+        if TimingEvent._hip is None:
+            TimingEvent._hip = ctypes.CDLL(os.path.join(torch.__path__[0], "lib", "libamdhip64.so"))
+        self._c = ctypes
+        self.stream = stream
+        self.e = ctypes.c_void_p()
+        rc = TimingEvent._hip.hipEventCreateWithFlags(ctypes.byref(self.e), ctypes.c_uint(self.FLAG))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+
+    def record(self):
+        rc = TimingEvent._hip.hipEventRecord(self.e, self._c.c_void_p(self.stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def elapsed_time(self, end) -> float:
+        ms = self._c.c_float()
+        rc = TimingEvent._hip.hipEventElapsedTime(self._c.byref(ms), self.e, end.e)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return ms.value
+
+    def __del__(self):
+        if TimingEvent._hip is not None and self.e:
+            TimingEvent._hip.hipEventDestroy(self.e)
+
+
 def gate_plan(circ, Q):
     import numpy as np
     D = circ.D
@@ -99,15 +135,16 @@ def bench_plain(args, Q, torch, circ):
         return Q.qd_norm2(s)
 
     def new_events(positions):
-        return {i: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for i in positions}
+        return {i: (TimingEvent(torch, stream), TimingEvent(torch, stream)) for i in positions}
 
     step(label=True)          # untimed: the first warm-up step also records each gate's kernel
     for _ in range(args.warmup - 1):
         step()
     # Untimed: one step with events around every gate, for the per-kernel breakdown and to find the
-    # dominant kernel. An event record costs a few microseconds of GPU time between two kernels:
-    # around all 500 gates it adds about 4 ms to a step, so the timed steps carry events only
-    # around the launches of the dominant kernel, whose average duration they measure.
+    # dominant kernel. Even without its system-scope fence an event record costs GPU time between
+    # two kernels (around all 500 gates about 2.4 ms a step, 3.8 ms with the fence), so the timed
+    # steps carry events only around the launches of the dominant kernel (about 0.4 ms a step),
+    # whose average duration they measure.
     full = new_events(range(len(plan)))
     step(full)
     torch.cuda.synchronize()
@@ -154,7 +191,7 @@ def bench_plain(args, Q, torch, circ):
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "timed_launches": len(dom_ms),
-                     "timing": "HIP events around each launch of the kernel in the timed steps (no other gate carries events there)"},
+                     "timing": "HIP events (no system-scope fence) around each launch of the kernel in the timed steps; no other gate carries events there"},
         "kernels": kernels,
     }
 
