@@ -905,7 +905,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(a multi-GPU run would shard the register, which this build does not do)", file=sys.stderr)
+              f"(a multi-GPU run would shard the register, which this library does not do)", file=sys.stderr)
         sys.exit(2)
     import torch
 
