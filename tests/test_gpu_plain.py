@@ -30,6 +30,25 @@ def stream():
     return torch_stream()
 
 
+def read_amplitudes(s, prec, idx):
+    """Amplitudes of a device state at flat indices, copied one by one (for states too large to
+    download whole)."""
+    import ctypes
+    import os
+    import torch
+    hip = ctypes.CDLL(os.path.join(torch.__path__[0], "lib", "libamdhip64.so"))
+    base = Q.qd_state_device_ptr(s)
+    esz, dt = (16, np.complex128) if prec == Q.QD_C128 else (8, np.complex64)
+    buf = (ctypes.c_char * esz)()
+    torch.cuda.synchronize()
+    out = np.empty(len(idx), np.complex128)
+    for k, i in enumerate(idx):
+        rc = hip.hipMemcpy(buf, ctypes.c_void_p(base + esz * int(i)), ctypes.c_size_t(esz), ctypes.c_int(2))
+        assert rc == 0, rc
+        out[k] = np.frombuffer(bytes(buf), dtype=dt)[0]
+    return out
+
+
 # ------------------------------------------------------------------------------ paper example
 def test_worked_example_bit_exact(stream):
     """Sec. 3.9 worked example: exactly 0.7071067811865475 at |000> and |120>."""
@@ -483,7 +502,8 @@ def test_tiled_kernel_walks_tiles_beyond_the_grid_cap(stream, prec):
     stages runs of 2 x 200 = 400 amplitudes for a gate on the last qubit, so the launch covers
     D / 400 = 8,388,608 tiles. The same gate through the direct kernel (run_min 1) on a complex128
     state prepared the same way is the reference: equal FP64 arithmetic for complex128, the
-    complex64 bound of five gates otherwise."""
+    complex64 bound of five gates otherwise; and the oracle at sampled outputs (the prepared state
+    is a product state the oracle evaluates amplitude by amplitude)."""
     dims = (2,) * 23 + (200, 2)
     n = len(dims)
     D = O.register_size(dims)
@@ -515,6 +535,27 @@ def test_tiled_kernel_walks_tiles_beyond_the_grid_cap(stream, prec):
         err, fid, drift = Q.qd_compare(states[1], states[0])
         tol = 1e-12 if prec == Q.QD_C128 else c64_tol(len(prep) + 1, 2)
         assert err <= tol and abs(fid) <= max(tol, 1e-12) and drift <= max(tol, 1e-12), (err, fid, drift)
+        # The oracle at sampled outputs of the tile kernel: the prepared state is the product of
+        # each prepared qubit's U|0> (|0> elsewhere), evaluated amplitude by amplitude; samples
+        # include the ends of the state and of tiles in both rounds of the workgroups' walk.
+        phi = {t[0]: U[:, 0] for t, U in prep}
+
+        class Prepared:
+            def __getitem__(self, i):
+                dg = O.digits_of(int(i), dims)
+                return complex(np.prod([phi[q][dg[q]] if q in phi else (1.0 if dg[q] == 0 else 0.0)
+                                        for q in range(n)]))
+
+        T = D // 400
+        idx = list(rng.choice(D, 600, replace=False))
+        for t in (0, 1, 2 ** 22 - 1, 2 ** 22, 2 ** 22 + 1, T - 1):
+            idx += [t * 400, t * 400 + 1, t * 400 + 199, t * 400 + 200, t * 400 + 399]
+        st = O.strides(dims)
+        idx += [D - 1] + [a * st[0] + b * st[11] + c * st[22] + e
+                          for a in (0, 1) for b in (0, 1) for c in (0, 1) for e in (0, 1)]
+        want = O.apply_gate_at(Prepared(), dims, (n - 1,), (), (), V, idx)
+        got = read_amplitudes(states[0], prec, idx)
+        assert max_abs(got, want) <= tol, max_abs(got, want)
     finally:
         for s in states:
             Q.qd_state_free(s)
