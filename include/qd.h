@@ -653,7 +653,7 @@ int qd_tune_set(int32_t param, int32_t value);
 int qd_tune_get(int32_t param, int32_t* value);
 
 /* Autotuner of the gate kernels: for each stride class of the smallest target stride (1, 2-3,
- * 4-15, 16-255, >= 256) present in the state's register, times a dense single-qudit gate with
+ * 4-15, 16-255, 256-4095, >= 4096) present in the state's register, times a dense single-qudit gate with
  * every candidate tile shape (direct: 64/128/256 threads x 1/2/4 slices per thread; LDS tile:
  * 512..4096 amplitudes x 128/256 threads) and keeps the fastest per (precision, stride class).
  * The state's amplitudes are overwritten: pass a scratch state. Writes the table as JSON to path

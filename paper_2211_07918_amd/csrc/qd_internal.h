@@ -65,7 +65,7 @@ TuneParams& tune();
 int batch_key(bool composed, int dT, int64_t min_stride);
 
 // Autotuned tile shape per (precision, stride class of the gate's smallest target stride).
-constexpr int kStrideBuckets = 5;   // strides 1 | 2-3 | 4-15 | 16-255 | >= 256
+constexpr int kStrideBuckets = 6;   // strides 1 | 2-3 | 4-15 | 16-255 | 256-4095 | >= 4096
 struct TuneEntry {
   int valid;
   int tiled;        // stage slices in LDS

@@ -4,6 +4,7 @@
 // a small JSON file (one entry per line).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -16,7 +17,12 @@ namespace qd {
 static TuneEntry g_table[2][kStrideBuckets];
 static bool g_table_valid = false;
 
-int stride_bucket(int64_t s) { return s < 2 ? 0 : (s < 4 ? 1 : (s < 16 ? 2 : (s < 256 ? 3 : 4))); }
+// Strides of 256 to 4095 amplitudes and larger ones are tuned apart: a direct-kernel shape chosen on
+// a gate whose two planes lie megabytes apart can be several percent off for planes a few
+// kilobytes apart, and the reverse.
+int stride_bucket(int64_t s) {
+  return s < 2 ? 0 : (s < 4 ? 1 : (s < 16 ? 2 : (s < 256 ? 3 : (s < 4096 ? 4 : 5))));
+}
 
 TuneEntry entry_for(int prec, int64_t min_stride) {
   const int b = stride_bucket(min_stride);
@@ -34,18 +40,24 @@ TuneEntry entry_for(int prec, int64_t min_stride) {
 
 void clear_tuned_table() { g_table_valid = false; }
 
+// Time of one launch: the fastest of five rounds of two launches each, after a warm-up. Candidates
+// a few percent apart are common (thread counts of the tile kernel, slices per thread), and noise
+// only ever adds time, so the minimum over rounds separates them where one average would not.
 static int time_gate(qd_state* s, const GatePlan& p, float* ms) {
   hipEvent_t e0, e1;
   QD_HIP(hipEventCreate(&e0));
   QD_HIP(hipEventCreate(&e1));
   int rc = launch_gate(s, p);  // warm-up (also compiles nothing: code objects are loaded)
-  if (!rc) {
-    QD_HIP(hipEventRecord(e0, s->stream));
-    for (int i = 0; i < 3 && !rc; ++i) rc = launch_gate(s, p);
-    QD_HIP(hipEventRecord(e1, s->stream));
-    QD_HIP(hipEventSynchronize(e1));
-    QD_HIP(hipEventElapsedTime(ms, e0, e1));
-    *ms /= 3.0f;
+  *ms = 1e30f;
+  for (int round = 0; round < 5 && !rc; ++round) {
+    float t = 0.f;
+    hipError_t e = hipEventRecord(e0, s->stream);
+    for (int i = 0; i < 2 && !rc && e == hipSuccess; ++i) rc = launch_gate(s, p);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess && !rc) rc = hip_fail(e, "autotune timing");
+    if (!rc) *ms = std::min(*ms, t / 2.0f);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
