@@ -263,6 +263,12 @@ int qd_probabilities(const qd_state* s, double* out, int32_t out_is_device);
  * Synchronises. */
 int qd_norm2(const qd_state* s, double* out);
 
+/* Both readouts of Sec. 3.8 / Eq. (1) from one pass over the state: the probabilities, as
+ * qd_probabilities writes them (out: D doubles, a device pointer when out_is_device != 0, else
+ * host memory), and ||psi||^2 into *norm2 (host), bitwise equal to what qd_norm2 returns (the same
+ * grid, visiting order and reduction tree). QD_EINVAL for a null argument. Synchronises. */
+int qd_probabilities_norm2(const qd_state* s, double* out, int32_t out_is_device, double* norm2);
+
 /* qd_norm2 for callers that cannot allocate device memory (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc): the same kernels and the same fixed reduction tree, so
  * the result is bitwise equal to qd_norm2's, written as one FP64 value to out_dev, a device

@@ -38,7 +38,7 @@ __all__ = [
     "qd_state_download", "qd_state_size", "qd_state_dims", "qd_state_precision", "qd_state_device_ptr",
     "qd_state_sync", "qd_state_free", "qd_apply_gate", "qd_apply_gate_ex", "qd_fuse_plan",
     "qd_fuse", "qd_fused_count", "qd_fused_block_info", "qd_fused_block_gates", "qd_fused_download_block",
-    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_norm2_noalloc", "qd_compare", "qd_compare_ex",
+    "qd_apply_fused", "qd_fused_free", "qd_probabilities", "qd_norm2", "qd_probabilities_norm2", "qd_norm2_noalloc", "qd_compare", "qd_compare_ex",
     "qd_normalize", "qd_sample", "qd_sample_device", "qd_marginals", "qd_support", "qd_ket_string", "kets",
     "qd_circuit_create", "qd_circuit_add", "qd_qasm_parse", "qd_circuit_size", "qd_circuit_dims", "qd_circuit_name",
     "qd_circuit_gate", "qd_circuit_gates", "qd_circuit_moments", "qd_circuit_decompose", "qd_circuit_apply",
@@ -133,6 +133,7 @@ _SIGS = {
     "qd_fused_free": (None, [_P]),
     "qd_probabilities": (C.c_int, [_P, _DP, C.c_int32]),
     "qd_norm2": (C.c_int, [_P, _DP]),
+    "qd_probabilities_norm2": (C.c_int, [_P, _DP, C.c_int32, _DP]),
     "qd_norm2_noalloc": (C.c_int, [_P, _P]),
     "qd_compare": (C.c_int, [_P, _P, _DP, _DP, _DP]),
     "qd_compare_ex": (C.c_int, [_P, _P, _DP]),
@@ -494,6 +495,18 @@ def qd_norm2(s: int) -> float:
     v = C.c_double()
     _check(load().qd_norm2(_P(s), C.byref(v)))
     return float(v.value)
+
+
+def qd_probabilities_norm2(s: int, out_dev_ptr: Optional[int] = None):
+    """Probabilities and ||psi||^2 from one pass: (None, norm2) with the probabilities written to
+    device memory at out_dev_ptr, or (NumPy array, norm2) when out_dev_ptr is None."""
+    v = C.c_double()
+    if out_dev_ptr is not None:
+        _check(load().qd_probabilities_norm2(_P(s), C.cast(_P(out_dev_ptr), _DP), 1, C.byref(v)))
+        return None, float(v.value)
+    out = np.empty(qd_state_size(s), dtype=np.float64)
+    _check(load().qd_probabilities_norm2(_P(s), _dptr(out), 0, C.byref(v)))
+    return out, float(v.value)
 
 
 def qd_norm2_noalloc(s: int, out_dev_ptr: int):

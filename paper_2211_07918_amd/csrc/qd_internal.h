@@ -194,6 +194,7 @@ int launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t st
 // Readout (qd_reduce.hip)
 int launch_probabilities(const qd_state* s, double* out_dev);
 int reduce_norm2(const qd_state* s, double* out);
+int reduce_probabilities_norm2(const qd_state* s, double* out_dev, double* norm2);   // one pass for both
 int reduce_norm2_noalloc(const qd_state* s, double* out_dev);   // partials in a static device array
 int reduce_compare(const qd_state* ref, const qd_state* s, double* max_abs, double* fid, double* drift,
                    double* norm2 = nullptr, double* fid_norm = nullptr);

@@ -23,17 +23,21 @@ static unsigned red_grid(uint64_t D) {
   return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(kRedMaxGrid, (D + kRedBlock * 8 - 1) / (kRedBlock * 8))));
 }
 
+// |alpha|^2 in FP64, written as one fused multiply-add so that the probability pass, the norm pass
+// and the fused pass below all round it the same way
+template <typename C>
+__device__ __forceinline__ double prob_of(const C a) {
+  const double re = double(a.x), im = double(a.y);
+  return fma(re, re, im * im);
+}
+
 // one amplitude per thread, streaming access (faster than a grid-stride loop on gfx950)
 template <typename R>
 __global__ __launch_bounds__(256) void k_probabilities(const R* psi_raw, double* __restrict__ p, uint64_t D) {
   using C = typename CxR<R>::T;
   const C* psi = reinterpret_cast<const C*>(psi_raw);
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < D) {
-    const C a = ld_stream(psi + i);
-    const double re = double(a.x), im = double(a.y);
-    __builtin_nontemporal_store(re * re + im * im, p + i);
-  }
+  if (i < D) __builtin_nontemporal_store(prob_of(ld_stream(psi + i)), p + i);
 }
 
 // NV values per thread, reduced by sum (slot < NSUM) or max (other slots)
@@ -63,10 +67,25 @@ __global__ __launch_bounds__(256) void k_norm_partial(const R* psi_raw, uint64_t
   using C = typename CxR<R>::T;
   const C* psi = reinterpret_cast<const C*>(psi_raw);
   double v[1] = {0.0};
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x)
+    v[0] += prob_of(ld_stream(psi + i));
+  block_reduce<1>(v, 1, partial + blockIdx.x);
+}
+
+// Probabilities and the norm's partial sums in one pass over the state: the grid, the amplitudes
+// each thread visits, their order and the tree are those of k_norm_partial, so the partials (and
+// the norm k_finish makes of them) are bitwise those of qd_norm2, and every probability is the value
+// k_probabilities writes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_probabilities_norm(const R* psi_raw, double* __restrict__ p, uint64_t D,
+                                                            double* partial) {
+  using C = typename CxR<R>::T;
+  const C* psi = reinterpret_cast<const C*>(psi_raw);
+  double v[1] = {0.0};
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < D; i += uint64_t(gridDim.x) * blockDim.x) {
-    const C a = ld_stream(psi + i);
-    const double re = double(a.x), im = double(a.y);
-    v[0] += re * re + im * im;
+    const double q = prob_of(ld_stream(psi + i));
+    __builtin_nontemporal_store(q, p + i);
+    v[0] += q;
   }
   block_reduce<1>(v, 1, partial + blockIdx.x);
 }
@@ -146,6 +165,25 @@ int reduce_norm2(const qd_state* cs, double* out) {
   hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(kRedBlock), 0, s->stream, s->red, g, 1, s->red + g);
   QD_HIP(hipGetLastError());
   QD_HIP(hipMemcpyAsync(out, s->red + g, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QD_HIP(hipStreamSynchronize(s->stream));
+  return QD_OK;
+}
+
+int reduce_probabilities_norm2(const qd_state* cs, double* out_dev, double* norm2) {
+  qd_state* s = const_cast<qd_state*>(cs);
+  const uint64_t D = uint64_t(s->reg.D);
+  const unsigned g = red_grid(D);
+  int rc = ensure_red(s, g + 8);
+  if (rc) return rc;
+  if (s->prec == QD_C128)
+    hipLaunchKernelGGL((k_probabilities_norm<double>), dim3(g), dim3(kRedBlock), 0, s->stream, (const double*)s->data,
+                       out_dev, D, s->red);
+  else
+    hipLaunchKernelGGL((k_probabilities_norm<float>), dim3(g), dim3(kRedBlock), 0, s->stream, (const float*)s->data,
+                       out_dev, D, s->red);
+  hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(kRedBlock), 0, s->stream, s->red, g, 1, s->red + g);
+  QD_HIP(hipGetLastError());
+  QD_HIP(hipMemcpyAsync(norm2, s->red + g, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   QD_HIP(hipStreamSynchronize(s->stream));
   return QD_OK;
 }

@@ -580,6 +580,22 @@ int qd_probabilities(const qd_state* s, double* out, int32_t out_is_device) {
   return rc;
 }
 
+int qd_probabilities_norm2(const qd_state* s, double* out, int32_t out_is_device, double* norm2) {
+  if (!s || !out || !norm2) return fail(QD_EINVAL, "null argument");
+  if (out_is_device) return reduce_probabilities_norm2(s, out, norm2);
+  double* dev = nullptr;
+  const size_t bytes = size_t(s->reg.D) * sizeof(double);
+  QD_HIP(hipMalloc((void**)&dev, bytes));
+  int rc = reduce_probabilities_norm2(s, dev, norm2);
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(out, dev, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "probabilities download");
+  }
+  (void)hipFree(dev);
+  return rc;
+}
+
 int qd_norm2(const qd_state* s, double* out) {
   if (!s || !out) return fail(QD_EINVAL, "null argument");
   return reduce_norm2(s, out);

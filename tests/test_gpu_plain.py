@@ -288,6 +288,34 @@ def test_readout_probabilities_norm_compare(stream):
     assert e.value.code == Q.QD_EDIM
 
 
+@pytest.mark.parametrize("prec", [Q.QD_C128, Q.QD_C64])
+def test_one_pass_probabilities_and_norm(stream, prec):
+    """qd_probabilities_norm2 against the two separate passes (probabilities bitwise those of
+    qd_probabilities, the norm bitwise that of qd_norm2, into host and device memory) and against
+    FP64 arithmetic on the downloaded state; complex128 also against the oracle. Registers smaller
+    than one workgroup, ragged, and larger than one round of the reduction grid (2048 workgroups of
+    256 threads, 524,288 amplitudes)."""
+    import torch
+    for dims, ngates, seed in (((3,), 2, 31), ((3, 4, 2, 5, 3), 30, 32), ((3,) * 12 + (2,), 40, 33)):
+        c = C.random_circuit(dims, ngates, C.seeded_rng(seed))
+        s = _state_of(c, stream, prec)
+        p_sep, n_sep = Q.qd_probabilities(s), Q.qd_norm2(s)
+        p_one, n_one = Q.qd_probabilities_norm2(s)
+        assert np.array_equal(p_one, p_sep) and n_one == n_sep, dims
+        dev = torch.empty(c.D, dtype=torch.float64, device="cuda")
+        none, n_dev = Q.qd_probabilities_norm2(s, dev.data_ptr())
+        assert none is None and n_dev == n_sep
+        assert np.array_equal(dev.cpu().numpy(), p_sep)
+        psi = Q.qd_state_download(s).astype(np.complex128)
+        p_host = psi.real ** 2 + psi.imag ** 2
+        assert np.max(np.abs(p_one - p_host)) <= 4e-16 * max(1.0, float(np.max(p_host))), dims
+        assert abs(n_one - float(np.sum(p_host))) <= 1e-12, dims
+        if prec == Q.QD_C128:
+            ref = O.run_circuit(c)
+            assert np.max(np.abs(p_one - O.probabilities(ref))) <= 1e-13
+            assert abs(n_one - O.norm2(ref)) <= 1e-12
+
+
 def test_validation_leaves_state_unchanged(stream):
     dims = (2, 3, 4)
     rng = C.seeded_rng(13)

@@ -382,6 +382,17 @@ def test_batch_create_rejects_before_device_work():
         assert e.value.code == code, (dims_list, prec)
 
 
+def test_readout_rejects_null_arguments():
+    """The readout calls check their pointers before any device work (this runs without a GPU)."""
+    import ctypes
+    lib = Q.load()
+    v = ctypes.c_double()
+    buf = (ctypes.c_double * 4)()
+    assert lib.qd_probabilities_norm2(None, buf, 0, ctypes.byref(v)) == Q.QD_EINVAL
+    assert lib.qd_norm2(None, ctypes.byref(v)) == Q.QD_EINVAL
+    assert lib.qd_probabilities(None, buf, 0) == Q.QD_EINVAL
+
+
 def test_batch_tuning_keys(tmp_path):
     """Per-key slices per thread of the batched kernel: range checks, and a save / load round trip
     that keeps every key."""
