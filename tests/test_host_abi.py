@@ -342,7 +342,7 @@ def test_tune_load_and_save(tmp_path):
     F4 = O.f_gate(4)
     assert Q.qd_gate_route(dims, Q.QD_C128, [2], [], [], F4) == Q.QD_ROUTE_DIRECT
     p = tmp_path / "tune.json"
-    # stride class 4 (>= 256) tiled: qudit 2 (stride 288) is staged in LDS
+    # stride class 4 (256-4095) tiled: qudit 2 (stride 288) is staged in LDS
     p.write_text('[\n{"prec": 0, "bucket": 4, "tiled": 1, "block": 256, "spt": 1, "tile_elems": 2048},\n'
                  '{"batch_block": 128, "batch_spt": 4, "batch_grid": 32, "batch_fuse": 6, "batch_spt_mid": 2, '
                  '"batch_spt_wide": 1}\n]\n')
@@ -369,6 +369,31 @@ def test_tune_load_and_save(tmp_path):
         Q.qd_tune_load(str(bad))
     with pytest.raises(Q.QDError):
         Q.qd_tune_load(str(tmp_path / "missing.json"))
+
+
+def test_tune_stride_classes_split_at_4096(tmp_path):
+    """Target strides of 256-4095 amplitudes (class 4) and of 4096 or more (class 5) take separate
+    tuned entries: a tiled entry for class 4 routes a complex64 qubit gate of stride 2048 to the LDS
+    tile kernel and leaves the qubit of stride 4096 on the direct kernel; class 5 entries load and
+    save; class 6 does not exist."""
+    dims = [2] * 14                       # qudit 1: stride 4096, qudit 2: stride 2048
+    X2 = O.x_gate(2, 1)
+    entry = '{"prec": 1, "bucket": %d, "tiled": %d, "block": 256, "spt": 1, "tile_elems": 4096}'
+    p = tmp_path / "tune.json"
+    try:
+        for b, tiled in ((4, 1), (5, 0)):
+            p.write_text("[\n" + entry % (b, tiled) + "\n]\n")
+            Q.qd_tune_load(str(p))
+            assert Q.qd_gate_route(dims, Q.QD_C64, [2], [], [], X2) == (Q.QD_ROUTE_TILED if b == 4 else Q.QD_ROUTE_DIRECT)
+            assert Q.qd_gate_route(dims, Q.QD_C64, [1], [], [], X2) == Q.QD_ROUTE_DIRECT
+            out = tmp_path / "saved.json"
+            Q.qd_tune_save(str(out))
+            assert ('"bucket": %d, "tiled": %d, "block": 256' % (b, tiled)) in out.read_text()
+        p.write_text("[\n" + entry % (6, 0) + "\n]\n")
+        with pytest.raises(Q.QDError):
+            Q.qd_tune_load(str(p))
+    finally:
+        Q.qd_tune_set(Q.QD_TUNE_RUN_MIN, 0)   # discards the loaded table
 
 
 def test_batch_create_rejects_before_device_work():
