@@ -32,3 +32,22 @@ def max_abs(a, b):
 def fidelity_loss(ref, psi):
     inner = np.vdot(np.asarray(ref, np.complex128), np.asarray(psi, np.complex128))
     return float(1.0 - abs(inner) ** 2)
+
+
+def read_amplitudes(s, prec, idx):
+    """Amplitudes of a device state at flat indices, copied one by one (for states too large to
+    download whole)."""
+    import ctypes
+    import os
+    import torch
+    hip = ctypes.CDLL(os.path.join(torch.__path__[0], "lib", "libamdhip64.so"))
+    base = Q.qd_state_device_ptr(s)
+    esz, dt = (16, np.complex128) if prec == Q.QD_C128 else (8, np.complex64)
+    buf = (ctypes.c_char * esz)()
+    torch.cuda.synchronize()
+    out = np.empty(len(idx), np.complex128)
+    for k, i in enumerate(idx):
+        rc = hip.hipMemcpy(buf, ctypes.c_void_p(base + esz * int(i)), ctypes.c_size_t(esz), ctypes.c_int(2))
+        assert rc == 0, rc
+        out[k] = np.frombuffer(bytes(buf), dtype=dt)[0]
+    return out

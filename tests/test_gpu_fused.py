@@ -20,7 +20,7 @@ import pytest
 import circuits as C
 import oracle as O
 import paper_2211_07918_amd as Q
-from gpu_util import fidelity_loss, max_abs, torch_stream
+from gpu_util import fidelity_loss, max_abs, read_amplitudes, torch_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -220,6 +220,62 @@ def test_brickwork_20_qutrits_full_size(stream, mode):
     finally:
         Q.qd_state_free(s)
         Q.qd_state_free(ref)
+        Q.qd_fused_free(f)
+
+
+@pytest.mark.parametrize("mode", GATED)
+def test_brickwork_20_qutrits_block_vs_oracle_samples(stream, mode):
+    """One 81 x 81 block on the 28 GB 20-qutrit register against the oracle at sampled outputs.
+    The input is a product state (every qutrit q in U_q|0> for a seeded Haar U_q, prepared on the
+    GPU by the plain complex64 path), which the oracle evaluates amplitude by amplitude; the block
+    is the product of three Haar 9 x 9 gates on qutrits (8, 9), (10, 11), (9, 10), which the oracle
+    builds as full operators of a 4-qutrit register. Samples: 400 seeded indices and the state's
+    ends. Bound, per output y = sum_c M[r, c] x_c, relative to b = sum_c |M[r, c]| |x_c| (which
+    the oracle also evaluates): the inputs carry the rounding of 20 complex64 gates (at most
+    3 x 2^-24 each, relative), and the block's real products sum 162 terms in FP32 (FP32 mode:
+    162 x 2^-24) or use operands split into BF16 pairs held to about 2^-16 (split-BF16 mode:
+    3 x 2^-16), so |y - y_oracle| <= c b with c = 60 x 2^-24 + 162 x 2^-24 (FP32) or
+    60 x 2^-24 + 3 x 2^-16 (split BF16, whose FP64 renormalisation moves each output by about 1e-6
+    of |y| <= b more)."""
+    dims = (3,) * 20
+    n = len(dims)
+    D = 3 ** 20
+    rng = C.seeded_rng(2020)
+    prep = [C.haar_unitary(3, rng) for _ in range(n)]
+    gates = [C.Gate("U", (8, 9), U=C.haar_unitary(9, rng)), C.Gate("U", (10, 11), U=C.haar_unitary(9, rng)),
+             C.Gate("U", (9, 10), U=C.haar_unitary(9, rng))]
+    circ = C.Circuit(dims, gates)
+    f = fuse(circ, 81, stream)
+    s = Q.qd_state_init(dims, Q.QD_C64, stream)
+    try:
+        assert Q.qd_fused_count(f) == 1 and Q.qd_fused_block_info(f, 0)["B"] == 81
+        Q.qd_state_set_basis(s, [0] * n)
+        for q, U in enumerate(prep):
+            Q.qd_apply_gate(s, (q,), (), (), U)
+        Q.qd_apply_fused(s, f, mode)
+        # the block as the oracle defines it: G3 G2 G1 on qutrits 8..11 (local 0..3)
+        w4 = (3, 3, 3, 3)
+        M = np.eye(81, dtype=np.complex128)
+        for g in gates:
+            M = O.gate_operator(w4, tuple(t - 8 for t in g.targets), (), (), g.U) @ M
+        phi = [U[:, 0] for U in prep]
+
+        class Prepared:
+            def __init__(self, vecs):
+                self.vecs = vecs
+
+            def __getitem__(self, i):
+                return complex(np.prod([self.vecs[q][d] for q, d in enumerate(O.digits_of(int(i), dims))]))
+
+        idx = list(rng.choice(D, 400, replace=False)) + [0, 1, D - 2, D - 1]
+        want = O.apply_gate_at(Prepared(phi), dims, (8, 9, 10, 11), (), (), M, idx)
+        bound = O.apply_gate_at(Prepared([np.abs(p) for p in phi]), dims, (8, 9, 10, 11), (), (), np.abs(M), idx).real
+        got = read_amplitudes(s, Q.QD_C64, idx)
+        c = 60 * 2.0 ** -24 + (162 * 2.0 ** -24 if mode == Q.QD_MODE_FP32_MFMA else 3 * 2.0 ** -16)
+        ratio = float(np.max(np.abs(np.asarray(got) - want) / bound))
+        assert ratio <= c, (ratio, c, max_abs(got, want))
+    finally:
+        Q.qd_state_free(s)
         Q.qd_fused_free(f)
 
 

@@ -14,7 +14,7 @@ import pytest
 import circuits as C
 import oracle as O
 import paper_2211_07918_amd as Q
-from gpu_util import fidelity_loss, max_abs, run_gpu, torch_stream
+from gpu_util import fidelity_loss, max_abs, read_amplitudes, run_gpu, torch_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -29,24 +29,6 @@ def c64_tol(ngates, dmax):
 def stream():
     return torch_stream()
 
-
-def read_amplitudes(s, prec, idx):
-    """Amplitudes of a device state at flat indices, copied one by one (for states too large to
-    download whole)."""
-    import ctypes
-    import os
-    import torch
-    hip = ctypes.CDLL(os.path.join(torch.__path__[0], "lib", "libamdhip64.so"))
-    base = Q.qd_state_device_ptr(s)
-    esz, dt = (16, np.complex128) if prec == Q.QD_C128 else (8, np.complex64)
-    buf = (ctypes.c_char * esz)()
-    torch.cuda.synchronize()
-    out = np.empty(len(idx), np.complex128)
-    for k, i in enumerate(idx):
-        rc = hip.hipMemcpy(buf, ctypes.c_void_p(base + esz * int(i)), ctypes.c_size_t(esz), ctypes.c_int(2))
-        assert rc == 0, rc
-        out[k] = np.frombuffer(bytes(buf), dtype=dt)[0]
-    return out
 
 
 # ------------------------------------------------------------------------------ paper example
