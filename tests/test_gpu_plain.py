@@ -30,7 +30,6 @@ def stream():
     return torch_stream()
 
 
-
 # ------------------------------------------------------------------------------ paper example
 def test_worked_example_bit_exact(stream):
     """Sec. 3.9 worked example: exactly 0.7071067811865475 at |000> and |120>."""
